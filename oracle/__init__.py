@@ -1,0 +1,155 @@
+"""FP64 oracle for ParChain-style hierarchical agglomerative clustering.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg use this package to check and time the GPU library. The GPU
+library never imports, loads or calls anything here, and this package imports
+nothing from the library.
+
+Contents
+  * ``nnchain``       sequential nearest-neighbour chain in FP64 (C, ``nnchain.c``)
+  * ``linkage_dist``  linkage distance of two explicit member sets (Table 1)
+  * ``canonical``     the dendrogram row convention (sorted rows, scipy ids)
+  * ``brute``         generic HAC by brute force, for tiny inputs (``brute.py``)
+
+Linkage codes: 0 complete, 1 average (mean Euclidean), 2 Ward.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nnchain.c")
+_LIBDIR = os.path.join(_HERE, "_build")
+_LIB = os.path.join(_LIBDIR, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+LINKAGES = {"complete": 0, "average": 1, "ward": 2}
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (OpenMP). Returns the library path."""
+    with _lock:
+        if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            os.makedirs(_LIBDIR, exist_ok=True)
+            tmp = _LIB + ".tmp%d" % os.getpid()
+            subprocess.check_call(
+                ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC, "-lm"]
+            )
+            os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        f64p = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_nnchain.restype = ctypes.c_int
+        lib.oracle_nnchain.argtypes = [
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            i64p, i64p, f64p, i64p, f64p,
+        ]
+        lib.oracle_linkage.restype = ctypes.c_double
+        lib.oracle_linkage.argtypes = [
+            ctypes.c_void_p, ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int64, i64p, ctypes.c_int64,
+        ]
+        _lib = lib
+    return _lib
+
+
+def _code(linkage) -> int:
+    return LINKAGES[linkage] if isinstance(linkage, str) else int(linkage)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def nnchain(x: np.ndarray, linkage, threads: int = 0):
+    """Sequential NN-chain HAC of float32 points ``x`` (n, d).
+
+    Returns ``(Z, cert)``: ``Z`` is (n-1, 4) float64 rows in merge order
+    ``[node_a, node_b, height, size]`` (leaves 0..n-1, merge k makes n+k);
+    ``cert`` holds the tie certificate: ``min_gap`` (smallest relative gap
+    between best and runner-up over all queries), ``zero_best``, ``queries``
+    and ``pair_evals``.
+    """
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    n, d = x.shape
+    m = max(n - 1, 1)
+    a = np.zeros(m, np.int64)
+    b = np.zeros(m, np.int64)
+    h = np.zeros(m, np.float64)
+    s = np.zeros(m, np.int64)
+    cert = np.zeros(4, np.float64)
+    rc = _load().oracle_nnchain(
+        x.ctypes.data, n, d, _code(linkage), int(threads),
+        _ptr(a, ctypes.c_int64), _ptr(b, ctypes.c_int64), _ptr(h, ctypes.c_double),
+        _ptr(s, ctypes.c_int64), _ptr(cert, ctypes.c_double),
+    )
+    if rc != 0:
+        raise ValueError("oracle_nnchain failed with code %d" % rc)
+    Z = np.stack([a, b, h, s], axis=1).astype(np.float64)[: n - 1]
+    return Z, dict(min_gap=cert[0], zero_best=int(cert[1]), queries=int(cert[2]),
+                   pair_evals=int(cert[3]))
+
+
+def linkage_dist(x: np.ndarray, linkage, A, B) -> float:
+    """Linkage distance between member index sets ``A`` and ``B`` (Table 1)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    A = np.ascontiguousarray(A, dtype=np.int64)
+    B = np.ascontiguousarray(B, dtype=np.int64)
+    return float(_load().oracle_linkage(
+        x.ctypes.data, x.shape[1], _code(linkage), _ptr(A, ctypes.c_int64), A.size,
+        _ptr(B, ctypes.c_int64), B.size))
+
+
+def members(Z: np.ndarray, n: int):
+    """Member lists of every node of a dendrogram in scipy convention."""
+    mem = [[i] for i in range(n)] + [None] * (n - 1)
+    for r in range(n - 1):
+        a, b = int(Z[r, 0]), int(Z[r, 1])
+        mem[n + r] = mem[a] + mem[b]
+    return mem
+
+
+def canonical(Z: np.ndarray, n: int) -> np.ndarray:
+    """Rows sorted by (height, size, lowest point index of the new cluster).
+
+    "height" here is the largest height in the row's subtree, which equals the
+    row's own height whenever the dendrogram is monotone (reducible linkages
+    in exact arithmetic); it keeps the order a valid creation order even if
+    rounding makes a parent a hair lower than a child.
+
+    Children are relabelled so that row r creates node n+r (scipy's
+    convention) and every row has a < b. A parent always has a larger size
+    than its children, so the order is also a valid creation order when
+    heights tie.
+    """
+    m = n - 1
+    if m <= 0:
+        return np.zeros((0, 4), np.float64)
+    lo = np.arange(n, dtype=np.int64).tolist() + [0] * m
+    eff = [0.0] * n + [0.0] * m
+    for r in range(m):
+        a, b = int(Z[r, 0]), int(Z[r, 1])
+        lo[n + r] = min(lo[a], lo[b])
+        eff[n + r] = max(float(Z[r, 2]), eff[a], eff[b])
+    key = [(eff[n + r], int(Z[r, 3]), lo[n + r]) for r in range(m)]
+    order = sorted(range(m), key=lambda r: key[r])
+    newid = list(range(n)) + [0] * m
+    for pos, r in enumerate(order):
+        newid[n + r] = n + pos
+    out = np.zeros((m, 4), np.float64)
+    for pos, r in enumerate(order):
+        a, b = newid[int(Z[r, 0])], newid[int(Z[r, 1])]
+        out[pos] = (min(a, b), max(a, b), Z[r, 2], Z[r, 3])
+    return out
