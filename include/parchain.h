@@ -1,0 +1,133 @@
+/*
+ * parchain.h - C ABI of libparchain.so: round-based parallel
+ * nearest-neighbour-chain hierarchical agglomerative clustering (HAC) on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problem (ParChain paper, Sec. 2 opening paragraph and Alg. 1): the input is
+ * a set of n points in R^d and a linkage criterion; the output is a
+ * dendrogram, here the n-1 merges (child a, child b, height, size), where the
+ * height of a merge is the linkage distance between the two clusters it
+ * joins (Table 1).
+ *
+ * Method (Alg. 1-4): every round finds the nearest active cluster of every
+ * chain tail ("terminal") with a range query whose radius comes from an upper
+ * bound on that distance (Sec. 4, Table 1 radii), then merges every pair of
+ * reciprocal nearest neighbours at once. Nearest-neighbour ties are broken by
+ * the cluster ID, the lowest point index in the cluster (Sec. 1 footnote).
+ *
+ * All functions are safe to call from C and C++ and never throw. Functions
+ * returning pc_status return PC_OK (0) or a negative error code; on error,
+ * pc_last_error() describes the failure and output buffers are unspecified.
+ */
+#ifndef PARCHAIN_H
+#define PARCHAIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PC_OK = 0,
+    PC_ERR_INVALID_ARG = -1,     /* NULL pointer, n < 1, d outside [1, 2048], n > 2^31-2, bad enum */
+    PC_ERR_NONFINITE_INPUT = -2, /* a coordinate is NaN or +-Inf */
+    PC_ERR_OUT_OF_MEMORY = -3,   /* device workspace does not fit */
+    PC_ERR_DEVICE = -4,          /* a HIP runtime call failed */
+    PC_ERR_UNSUPPORTED = -5,     /* valid request this build does not serve */
+    PC_ERR_BUSY = -6,            /* context in use by another thread */
+    PC_ERR_CANCELLED = -7
+} pc_status;
+
+/* Linkage criteria of Table 1 (Euclidean distances). */
+typedef enum {
+    PC_LINK_COMPLETE = 0, /* max over x in A, y in B of ||x-y|| */
+    PC_LINK_AVERAGE = 1,  /* "avg-1": mean over x in A, y in B of ||x-y|| */
+    PC_LINK_WARD = 2      /* sqrt(2|A||B|/(|A|+|B|)) * ||mean(A)-mean(B)|| */
+} pc_linkage;
+
+typedef enum {
+    PC_PREC_EXACT = 0 /* every decision and height from FP64 arithmetic on the
+                         float32 inputs (FP32 inputs widened exactly) */
+} pc_precision;
+
+/* One dendrogram row, scipy linkage-matrix convention: leaves are 0..n-1,
+ * row r creates cluster n+r, a < b. Rows are sorted by (height, size, lowest
+ * point index of the new cluster); "height" in that key is the largest
+ * height in the row's subtree (equal to the row's own height when the
+ * dendrogram is monotone). 32 bytes. */
+typedef struct {
+    int64_t a, b;
+    double height;
+    int64_t size;
+} pc_merge;
+
+/* Options; pass NULL for defaults. struct_size must be sizeof(pc_options). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t precision; /* pc_precision, default PC_PREC_EXACT */
+    int32_t prune;     /* 1 (default): range-query pruning (Sec. 4);
+                          0: every terminal scans every active cluster
+                          (same result, for ablations and tests) */
+    int32_t reserved;
+} pc_options;
+
+/* Counters of one pc_hac call; struct_size must be sizeof(pc_stats). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t reserved;
+    int64_t rounds;           /* rounds of Alg. 1 */
+    int64_t terminals;        /* sum over rounds of |Z| (terminal clusters) */
+    int64_t cluster_evals;    /* cluster-pair linkage distances computed */
+    int64_t point_pair_evals; /* point-pair distances computed ("D") */
+    int64_t overflow_queries; /* terminals served by the full-scan kernel */
+    double ms_total;          /* device time of the call (HIP events) */
+    double ms_init;           /* layout + first grid */
+    double ms_rounds;         /* all rounds */
+    double ms_finalize;       /* sort rows + relabel */
+} pc_stats;
+
+typedef struct pc_context pc_context;
+
+/*
+ * Create a context on HIP device `device` (the caller's current device if
+ * device < 0). The context owns the device workspace, grown on demand and
+ * reused across calls; it is not thread-safe (concurrent calls on one
+ * context return PC_ERR_BUSY).
+ */
+pc_status pc_context_create(int device, pc_context **out);
+void pc_context_destroy(pc_context *ctx);
+
+/* Device bytes pc_hac needs for (n, d, linkage); 0 on bad arguments. */
+size_t pc_hac_workspace_bytes(int64_t n, int32_t d, int32_t linkage, const pc_options *opt);
+
+/*
+ * Cluster n points (float32, row-major n x d) under `linkage`.
+ *   points           device pointer if points_on_device != 0, else host
+ *   out              n-1 rows (pc_merge); device pointer if out_on_device
+ *   stream           hipStream_t to order the work on, or NULL (legacy
+ *                    default stream); the call returns when the rows are
+ *                    written (it synchronises the stream)
+ *   stats            optional counters
+ * n == 1 returns PC_OK and writes nothing. Inputs are validated before any
+ * clustering work: NULL pointers, n < 1, d outside [1, 2048], n > 2^31-2 and unknown enums
+ * give PC_ERR_INVALID_ARG; NaN/Inf coordinates give PC_ERR_NONFINITE_INPUT.
+ * The caller keeps ownership of `points` and `out`; the library keeps no
+ * reference to them after the call returns.
+ */
+pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int points_on_device,
+                 int32_t linkage, const pc_options *opt, pc_merge *out, int out_on_device,
+                 void *stream, pc_stats *stats);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *pc_last_error(void);
+
+/* Library version string. */
+const char *pc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARCHAIN_H */

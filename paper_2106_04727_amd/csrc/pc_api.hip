@@ -1,0 +1,384 @@
+// C ABI of libparchain.so (declared in include/parchain.h) and the host side
+// of the round loop: validation, workspace layout, the per-round launches and
+// the few counter reads that size the next launches.
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/parchain.h"
+#include "pc_common.hpp"
+
+using namespace pc;
+
+namespace {
+
+thread_local std::string g_err;
+
+pc_status fail(pc_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(call)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(e_ == hipErrorOutOfMemory ? PC_ERR_OUT_OF_MEMORY : PC_ERR_DEVICE,            \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                          \
+  } while (0)
+
+// Carves typed arrays out of one device allocation (or only counts bytes when
+// base is null), 256-byte aligned.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_points,
+              float **xin = nullptr, pc_merge **rows_out = nullptr) {
+  Carver c{base};
+  const size_t n = (size_t)n64;
+  const bool pts = linkage != kWard;
+  S.cid = c.take<int>(n);
+  S.csize = c.take<int>(n);
+  S.node = c.take<int>(n);
+  S.succ = c.take<int>(n);
+  S.succ_node = c.take<int>(n);
+  S.predd = c.take<unsigned>(n);
+  S.term_round = c.take<int>(n);
+  S.alive = c.take<int>(n);
+  S.mdst = c.take<int>(n);
+  S.moff = c.take<int>(n);
+  S.cbeg = c.take<int>(pts ? n : 1);
+  S.nbeg = c.take<int>(pts ? n : 1);
+  S.eff = c.take<double>(n);
+  S.nn_h = c.take<double>(n);
+  S.wsum = c.take<double>(n * d);
+  S.wcen = c.take<double>(n * d);
+  S.lo = c.take<float>(pts ? n * d : 1);
+  S.hi = c.take<float>(pts ? n * d : 1);
+  S.act = c.take<int>(n);
+  S.act2 = c.take<int>(n);
+  S.term = c.take<int>(n);
+  S.flags = c.take<int>(n);
+  S.scan = c.take<int>(n + 1);
+  S.ovf = c.take<int>(n);
+  const bool grid = d <= kGridMaxDim;
+  const size_t cells = grid ? 2 * n + 16 : 1;
+  S.cell_cap = (int)cells;
+  S.cell_cnt = c.take<int>(cells + 1);
+  S.cell_start = c.take<int>(cells + 1);
+  S.cell_of = c.take<int>(n);
+  S.cell_rank = c.take<int>(n);
+  S.item_slot = c.take<int>(grid ? n : 1);
+  S.item_meta = c.take<int4>(grid ? n : 1);
+  S.item_cen = c.take<double>(grid ? n * d : 1);
+  S.item_lo = c.take<float>(grid && pts ? n * d : 1);
+  S.item_hi = c.take<float>(grid && pts ? n * d : 1);
+  S.t_best = c.take<double>(n);
+  S.t_key = c.take<unsigned long long>(n);
+  S.t_beta = c.take<double>(n);
+  S.t_min = c.take<unsigned long long>(n);
+  S.m_a = c.take<int>(n / 2 + 1);
+  S.m_b = c.take<int>(n / 2 + 1);
+  S.m_h = c.take<double>(n / 2 + 1);
+  S.row_na = c.take<int>(n);
+  S.row_nb = c.take<int>(n);
+  S.row_size = c.take<int>(n);
+  S.row_lo = c.take<int>(n);
+  S.row_h = c.take<double>(n);
+  S.row_eff = c.take<double>(n);
+  S.px = c.take<float>(pts ? n * d : 1);
+  S.px2 = c.take<float>(pts ? n * d : 1);
+  S.powner = c.take<int>(pts ? n : 1);
+  S.powner2 = c.take<int>(pts ? n : 1);
+  S.sk0 = c.take<unsigned long long>(n);
+  S.sk1 = c.take<unsigned long long>(n);
+  S.sv0 = c.take<unsigned>(n);
+  S.sv1 = c.take<unsigned>(n);
+  S.hist = c.take<int>((size_t)radix_hist_len((int)n) + 1);
+  S.grid = c.take<GridParams>(1);
+  S.cnt = c.take<Counters>(1);
+  // staging: input points (if on the host) and output rows (if on the host)
+  float *x = c.take<float>(host_points ? n * d : 1);
+  pc_merge *r = c.take<pc_merge>(n);
+  if (xin) *xin = x;
+  if (rows_out) *rows_out = r;
+  return c.off + 256;
+}
+
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+hipError_t grow(Buf &b, size_t bytes) {
+  if (b.bytes >= bytes) return hipSuccess;
+  if (b.p) hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e == hipSuccess) b.bytes = bytes;
+  return e;
+}
+
+}  // namespace
+
+struct pc_context {
+  int device = 0;
+  Buf ws, pairs, tiles, part;
+  Counters *hcnt = nullptr;  // pinned host mirror of the device counters
+  hipEvent_t ev[4] = {};
+  std::atomic<int> busy{0};
+};
+
+extern "C" {
+
+const char *pc_last_error(void) { return g_err.c_str(); }
+
+const char *pc_version(void) { return "parchain-mi355x 0.1 (gfx950)"; }
+
+pc_status pc_context_create(int device, pc_context **out) {
+  if (!out) return fail(PC_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int dev = device;
+  if (dev < 0) HIPCHK(hipGetDevice(&dev));
+  int count = 0;
+  HIPCHK(hipGetDeviceCount(&count));
+  if (dev >= count) return fail(PC_ERR_INVALID_ARG, "device index out of range");
+  HIPCHK(hipSetDevice(dev));
+  pc_context *c = new (std::nothrow) pc_context();
+  if (!c) return fail(PC_ERR_OUT_OF_MEMORY, "host allocation failed");
+  c->device = dev;
+  hipError_t e = hipHostMalloc((void **)&c->hcnt, sizeof(Counters), hipHostMallocDefault);
+  for (int i = 0; e == hipSuccess && i < 4; ++i) e = hipEventCreate(&c->ev[i]);
+  if (e != hipSuccess) {
+    pc_context_destroy(c);
+    return fail(PC_ERR_DEVICE, std::string("context setup: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  g_err.clear();
+  return PC_OK;
+}
+
+void pc_context_destroy(pc_context *c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  if (c->ws.p) hipFree(c->ws.p);
+  if (c->pairs.p) hipFree(c->pairs.p);
+  if (c->tiles.p) hipFree(c->tiles.p);
+  if (c->part.p) hipFree(c->part.p);
+  if (c->hcnt) hipHostFree(c->hcnt);
+  for (int i = 0; i < 4; ++i)
+    if (c->ev[i]) hipEventDestroy(c->ev[i]);
+  delete c;
+}
+
+size_t pc_hac_workspace_bytes(int64_t n, int32_t d, int32_t linkage, const pc_options *opt) {
+  (void)opt;
+  if (n < 1 || d < 1 || d > kMaxDim || n > 2147483646LL || linkage < 0 || linkage > 2) return 0;
+  State S;
+  size_t bytes = layout(S, nullptr, n, d, linkage, true);
+  if (linkage != kWard) {
+    const size_t pc = (size_t)std::max<int64_t>(1 << 20, 2 * n);
+    bytes += pc * (2 * sizeof(int) + sizeof(double) + sizeof(long long)) + 1024;
+    if (linkage == kAverage) bytes += ((size_t)1 << 22) * sizeof(double);
+  }
+  return bytes;
+}
+
+// Scan partials: one per 1024 elements of the longest scan of the call.
+static pc_status grow_part(pc_context *ctx, State &S, long long longest_scan) {
+  const long long need = longest_scan / 1024 + 1024;
+  HIPCHK(grow(ctx->part, (size_t)need * sizeof(long long)));
+  S.part = (long long *)ctx->part.p;
+  S.part_cap = (long long)(ctx->part.bytes / sizeof(long long));
+  return PC_OK;
+}
+
+static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
+  const size_t per = 2 * sizeof(int) + sizeof(double) + sizeof(long long);
+  HIPCHK(grow(ctx->pairs, (size_t)cap * per + 1024));
+  char *b = (char *)ctx->pairs.p;
+  S.pair_cap = (long long)((ctx->pairs.bytes - 1024) / per);
+  S.pr_tile0 = (long long *)b;
+  S.pr_v = (double *)(b + S.pair_cap * sizeof(long long));
+  S.pr_t = (int *)(b + S.pair_cap * (sizeof(long long) + sizeof(double)));
+  S.pr_c = S.pr_t + S.pair_cap;
+  return grow_part(ctx, S, std::max<long long>(S.pair_cap, 2LL * S.n + 64));
+}
+
+static pc_status grow_tiles(pc_context *ctx, State &S, long long cap) {
+  HIPCHK(grow(ctx->tiles, (size_t)cap * sizeof(double)));
+  S.tile_v = (double *)ctx->tiles.p;
+  S.tile_cap = (long long)(ctx->tiles.bytes / sizeof(double));
+  return PC_OK;
+}
+
+pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int points_on_device,
+                 int32_t linkage, const pc_options *opt, pc_merge *out, int out_on_device, void *stream,
+                 pc_stats *stats) {
+  if (!ctx) return fail(PC_ERR_INVALID_ARG, "context is NULL");
+  if (!points) return fail(PC_ERR_INVALID_ARG, "points is NULL");
+  if (n < 1) return fail(PC_ERR_INVALID_ARG, "n must be >= 1");
+  if (n > 2147483646LL) return fail(PC_ERR_INVALID_ARG, "n must be <= 2^31-2");
+  if (d < 1 || d > kMaxDim) return fail(PC_ERR_INVALID_ARG, "d must be in [1, 2048]");
+  if (linkage < 0 || linkage > 2) return fail(PC_ERR_INVALID_ARG, "unknown linkage");
+  if (n > 1 && !out) return fail(PC_ERR_INVALID_ARG, "out is NULL");
+  if (opt && opt->struct_size != sizeof(pc_options)) return fail(PC_ERR_INVALID_ARG, "pc_options.struct_size");
+  if (stats && stats->struct_size != sizeof(pc_stats)) return fail(PC_ERR_INVALID_ARG, "pc_stats.struct_size");
+  const int prune = opt ? (opt->prune != 0) : 1;
+  if (opt && opt->precision != PC_PREC_EXACT) return fail(PC_ERR_UNSUPPORTED, "precision mode not available");
+  if (!points_on_device) {
+    for (int64_t i = 0; i < n * (int64_t)d; ++i)
+      if (!std::isfinite(points[i])) return fail(PC_ERR_NONFINITE_INPUT, "non-finite coordinate");
+  }
+  int expected = 0;
+  if (!ctx->busy.compare_exchange_strong(expected, 1)) return fail(PC_ERR_BUSY, "context in use");
+  struct Release {
+    pc_context *c;
+    ~Release() { c->busy.store(0); }
+  } release{ctx};
+
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (stats) {
+    uint32_t ss = stats->struct_size;
+    memset(stats, 0, sizeof(*stats));
+    stats->struct_size = ss;
+  }
+  if (n == 1) {
+    g_err.clear();
+    return PC_OK;
+  }
+
+  State S;
+  memset(&S, 0, sizeof(S));
+  const size_t need = layout(S, nullptr, n, d, linkage, !points_on_device);
+  HIPCHK(grow(ctx->ws, need));
+  float *xstage = nullptr;
+  pc_merge *rstage = nullptr;
+  layout(S, (char *)ctx->ws.p, n, d, linkage, !points_on_device, &xstage, &rstage);
+  S.n = (int)n;
+  S.d = d;
+  S.linkage = linkage;
+  S.prune = prune;
+  float *xdev = (float *)points;
+  if (!points_on_device) {
+    xdev = xstage;
+    HIPCHK(hipMemcpyAsync(xdev, points, (size_t)n * d * sizeof(float), hipMemcpyHostToDevice, s));
+  }
+  pc_merge *dout = out_on_device ? out : rstage;
+
+  {
+    pc_status st = grow_part(ctx, S, 2LL * n + 64);
+    if (st != PC_OK) return st;
+  }
+  if (linkage != kWard) {
+    pc_status st = grow_pairs(ctx, S, std::max<long long>(1 << 20, 2 * n));
+    if (st != PC_OK) return st;
+    st = grow_tiles(ctx, S, linkage == kAverage ? (1 << 22) : 1);
+    if (st != PC_OK) return st;
+  }
+
+  HIPCHK(hipMemsetAsync(S.cnt, 0, sizeof(Counters), s));
+  HIPCHK(hipEventRecord(ctx->ev[0], s));
+  if (points_on_device) {
+    launch_check_finite(xdev, (long long)n * d, S.cnt, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ctx->hcnt, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (ctx->hcnt->nonfinite) return fail(PC_ERR_NONFINITE_INPUT, "non-finite coordinate");
+  }
+  launch_init(S, xdev, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(ctx->ev[1], s));
+
+  int nact = (int)n;
+  int merges = 0;
+  long long rounds = 0, terms = 0, ovfq = 0;
+  Counters &h = *ctx->hcnt;
+  while (nact > 1) {
+    if (rounds > n) return fail(PC_ERR_DEVICE, "round loop did not converge");
+    bool need_pairs = false;
+    launch_round(S, (int)rounds, nact, s, need_pairs);
+    HIPCHK(hipGetLastError());
+    if (need_pairs) {
+      HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (h.n_pairs > S.pair_cap) {
+        pc_status st = grow_pairs(ctx, S, (long long)h.n_pairs + h.n_pairs / 2 + 1024);
+        if (st != PC_OK) return st;
+        launch_round(S, (int)rounds, nact, s, need_pairs);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h.n_pairs > S.pair_cap) return fail(PC_ERR_DEVICE, "pair list overflow");
+      }
+      const int np = h.n_pairs;
+      launch_pairs_prefix(S, np, s);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const long long nt = np > 0 ? h.n_tiles : 0;
+      if (linkage == kAverage && nt > S.tile_cap) {
+        pc_status st = grow_tiles(ctx, S, nt + nt / 2 + 1024);
+        if (st != PC_OK) return st;
+      }
+      launch_pairs(S, (int)rounds, np, nt, s);
+      HIPCHK(hipGetLastError());
+    }
+    launch_round_tail(S, (int)rounds, nact, merges, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h.nonfinite == 2) return fail(PC_ERR_DEVICE, "a terminal found no neighbour");
+    if (h.nonfinite == 3) return fail(PC_ERR_DEVICE, "internal index check failed");
+    if (h.n_merge <= 0) return fail(PC_ERR_DEVICE, "round merged nothing");
+    terms += h.n_term;
+    ovfq += h.n_ovf;
+    merges += h.n_merge;
+    nact = h.n_act;
+    ++rounds;
+  }
+  if (merges != n - 1) return fail(PC_ERR_DEVICE, "merge count mismatch");
+  HIPCHK(hipEventRecord(ctx->ev[2], s));
+  launch_finalize(S, dout, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(ctx->ev[3], s));
+  if (!out_on_device)
+    HIPCHK(hipMemcpyAsync(out, dout, (size_t)(n - 1) * sizeof(pc_merge), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (stats) {
+    float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+    hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
+    hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
+    hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]);
+    hipEventElapsedTime(&t03, ctx->ev[0], ctx->ev[3]);
+    stats->rounds = rounds;
+    stats->terminals = terms;
+    stats->cluster_evals = h.cluster_evals;
+    stats->point_pair_evals = h.point_pairs;
+    stats->overflow_queries = ovfq;
+    stats->ms_init = t01;
+    stats->ms_rounds = t12;
+    stats->ms_finalize = t23;
+    stats->ms_total = t03;
+  }
+  g_err.clear();
+  return PC_OK;
+}
+
+}  // extern "C"

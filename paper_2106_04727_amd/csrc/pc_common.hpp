@@ -1,0 +1,155 @@
+// Shared declarations of libparchain: device helpers, the per-call device
+// state, and the launch wrappers each translation unit exports to the host
+// driver. gfx950 only (64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace pc {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kMaxDim = 2048;      // largest d accepted (full-scan kernel stages d coords in LDS)
+constexpr int kGridMaxDim = 16;    // ring search over a centroid grid up to this d
+constexpr int kInlinePairs = 64;   // |t|*|C| at or below this: evaluated inside the search
+constexpr int kTile = 64;          // point-pair tile edge for deferred evaluations
+constexpr uint32_t kInfBits = 0x7f800000u;
+
+enum Linkage { kComplete = 0, kAverage = 1, kWard = 2 };
+
+// ---------------------------------------------------------------- helpers --
+__device__ __forceinline__ unsigned long long ordered_bits(double v) {
+  // monotone map of doubles to unsigned 64-bit integers (for atomic min/max)
+  unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double from_ordered_bits(unsigned long long b) {
+  b = (b >> 63) ? (b & 0x7fffffffffffffffull) : ~b;
+  return __longlong_as_double((long long)b);
+}
+// For non-negative doubles the raw IEEE bits already order like the values.
+__device__ __forceinline__ unsigned long long pos_bits(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+__device__ __forceinline__ double pos_from_bits(unsigned long long b) {
+  return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  const int lane = threadIdx.x & (kWave - 1);
+  return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// --------------------------------------------------------- device state ----
+// Grid over cluster centroids (first one or two coordinates), square cells.
+struct GridParams {
+  double org[2];
+  double h;
+  double inv_h;
+  int G[2];
+  int ncell;
+  int ncell1;  // ncell + 1 (scan length of the cell counts)
+  int axes;
+};
+
+// Counters the device updates and the host reads once per round.
+struct Counters {
+  int n_act;
+  int n_term;
+  int n_merge;
+  int n_ovf;
+  int n_pairs;
+  int pair_overflow;
+  int n_min;
+  int nonfinite;
+  unsigned long long bb_lo[2];
+  unsigned long long bb_hi[2];
+  long long cluster_evals;
+  long long point_pairs;
+  long long n_tiles;
+  long long pad;
+};
+
+// All device arrays of one clustering call. Slots are storage indices of
+// clusters (capacity n); a merged cluster keeps the slot of its child with
+// the lower cluster ID. Lists hold slots.
+struct State {
+  int n, d, linkage, prune;
+  // per slot
+  int *cid;        // cluster ID = lowest original point index
+  int *csize;
+  int *node;       // dendrogram node id (leaf: point index; merge k: n+k)
+  int *succ;       // slot of the nearest neighbour, -1 if none
+  int *succ_node;  // node id of that neighbour when it was found
+  unsigned *predd; // float bits (rounded up) of the smallest distance from a predecessor
+  int *term_round; // round in which the slot was last a terminal
+  int *alive;
+  int *mdst, *moff;  // where a slot's points go in the next layout
+  int *cbeg, *nbeg;  // start of the cluster's point range (current / next)
+  double *eff;     // largest height in the cluster's subtree
+  double *nn_h;    // linkage distance to succ
+  double *wsum;    // d coordinate sums per slot (FP64)
+  double *wcen;    // d centroid coordinates per slot (wsum / csize)
+  float *lo, *hi;  // d-dimensional bounding box per slot (complete, average)
+  // lists
+  int *act, *act2, *term, *flags, *scan, *ovf;
+  // grid over active centroids
+  int *cell_cnt, *cell_start, *cell_of, *cell_rank;
+  int *item_slot;
+  int4 *item_meta;    // (slot, size, cid, 0)
+  double *item_cen;   // d per item
+  float *item_lo, *item_hi;
+  // per terminal
+  double *t_best;                 // value of the best inline candidate
+  unsigned long long *t_key;      // (cid << 32 | slot) of the best candidate
+  double *t_beta;                 // search bound (complete, average)
+  unsigned long long *t_min;      // bits of the smallest value (complete, average)
+  // merges
+  int *m_a, *m_b;
+  double *m_h;
+  // rows, creation order
+  int *row_na, *row_nb, *row_size, *row_lo;
+  double *row_h, *row_eff;
+  // points, permuted so that every cluster is a contiguous range
+  float *px, *px2;
+  int *powner, *powner2;
+  // sort scratch
+  unsigned long long *sk0, *sk1;
+  unsigned *sv0, *sv1;
+  int *hist;
+  long long *part;  // scan partials (growable with the pair list)
+  long long part_cap;
+  GridParams *grid;
+  Counters *cnt;
+  // deferred pair evaluations (growable, owned by the context)
+  int *pr_t, *pr_c;
+  double *pr_v;
+  long long *pr_tile0;  // exclusive prefix of tiles per pair
+  double *tile_v;
+  long long pair_cap, tile_cap;
+  int cell_cap;
+};
+
+// ------------------------------------------------------ launch wrappers ----
+// primitives (pc_prims.hip)
+void scan_exclusive_i32(const int *in, int *out, int nmax, const int *dlen, int *dtotal,
+                        long long *part, hipStream_t s);
+void scan_exclusive_i64(const long long *in, long long *out, int nmax, const int *dlen,
+                        long long *dtotal, long long *part, hipStream_t s);
+// stable radix sort of (key, value) pairs by the low `bits` bits of key
+void radix_sort_pairs(unsigned long long *&k0, unsigned long long *&k1, unsigned *&v0,
+                      unsigned *&v1, int n, int bits, int *hist, long long *part, hipStream_t s);
+int radix_hist_len(int n);
+
+// round kernels (pc_round.hip)
+void launch_check_finite(const float *x, long long count, Counters *cnt, hipStream_t s);
+void launch_init(State &S, const float *x, hipStream_t s);
+void launch_round(State &S, int round, int nact_host, hipStream_t s, bool &need_pairs);
+void launch_pairs(State &S, int round, int npairs_host, long long ntiles_host, hipStream_t s);
+void launch_pairs_prefix(State &S, int npairs_host, hipStream_t s);
+void launch_round_tail(State &S, int round, int nact_host, int merges_before, hipStream_t s);
+void launch_finalize(State &S, void *out_rows, hipStream_t s);
+
+}  // namespace pc

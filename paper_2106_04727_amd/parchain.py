@@ -1,0 +1,209 @@
+"""ctypes binding of libparchain.so (C ABI in include/parchain.h).
+
+Names follow the C functions. Only argument marshalling happens here: torch
+provides device memory and the stream, every step of the clustering runs in
+the library's HIP kernels. There is no fallback: if the library is missing
+or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libparchain.so")
+
+LINKAGES = {"complete": 0, "average": 1, "ward": 2}
+
+PC_OK = 0
+STATUS = {
+    0: "PC_OK",
+    -1: "PC_ERR_INVALID_ARG",
+    -2: "PC_ERR_NONFINITE_INPUT",
+    -3: "PC_ERR_OUT_OF_MEMORY",
+    -4: "PC_ERR_DEVICE",
+    -5: "PC_ERR_UNSUPPORTED",
+    -6: "PC_ERR_BUSY",
+    -7: "PC_ERR_CANCELLED",
+}
+
+
+class PCError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class pc_merge(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_int64), ("b", ctypes.c_int64), ("height", ctypes.c_double),
+                ("size", ctypes.c_int64)]
+
+
+class pc_options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("prune", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class pc_stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("rounds", ctypes.c_int64), ("terminals", ctypes.c_int64),
+                ("cluster_evals", ctypes.c_int64), ("point_pair_evals", ctypes.c_int64),
+                ("overflow_queries", ctypes.c_int64), ("ms_total", ctypes.c_double),
+                ("ms_init", ctypes.c_double), ("ms_rounds", ctypes.c_double),
+                ("ms_finalize", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("struct_size", "reserved")}
+
+
+_lib = None
+_lock = threading.Lock()
+
+EXPORTS = ["pc_context_create", "pc_context_destroy", "pc_hac_workspace_bytes", "pc_hac",
+           "pc_last_error", "pc_version"]
+
+
+def load_library(path: str | None = None):
+    """Load libparchain.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    with _lock:
+        if _lib is not None and path is None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise OSError("libparchain.so not built (%s); run __graft_entry__.build()" % p)
+        lib = ctypes.CDLL(p)
+        vp = ctypes.c_void_p
+        lib.pc_context_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+        lib.pc_context_create.restype = ctypes.c_int
+        lib.pc_context_destroy.argtypes = [vp]
+        lib.pc_context_destroy.restype = None
+        lib.pc_hac_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp]
+        lib.pc_hac_workspace_bytes.restype = ctypes.c_size_t
+        lib.pc_hac.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
+                               vp, vp, ctypes.c_int, vp, vp]
+        lib.pc_hac.restype = ctypes.c_int
+        lib.pc_last_error.argtypes = []
+        lib.pc_last_error.restype = ctypes.c_char_p
+        lib.pc_version.argtypes = []
+        lib.pc_version.restype = ctypes.c_char_p
+        if path is None:
+            _lib = lib
+        return lib
+
+
+def version() -> str:
+    return load_library().pc_version().decode()
+
+
+def _check(lib, st: int):
+    if st != PC_OK:
+        raise PCError(st, lib.pc_last_error().decode())
+
+
+def _link(linkage) -> int:
+    return LINKAGES[linkage] if isinstance(linkage, str) else int(linkage)
+
+
+def workspace_bytes(n: int, d: int, linkage) -> int:
+    return int(load_library().pc_hac_workspace_bytes(n, d, _link(linkage), None))
+
+
+class Context:
+    """A pc_context on one HIP device (owns the device workspace)."""
+
+    def __init__(self, device: int = -1):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.pc_context_create(int(device), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pc_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hac(self, points, n: int, d: int, linkage, out, *, points_on_device: bool,
+            out_on_device: bool, stream=None, prune: bool = True, stats: bool = True):
+        """Raw call: ``points``/``out`` are integer addresses."""
+        opt = pc_options(ctypes.sizeof(pc_options), 0, 1 if prune else 0, 0)
+        st = pc_stats()
+        st.struct_size = ctypes.sizeof(pc_stats)
+        rc = self.lib.pc_hac(self.handle, ctypes.c_void_p(points), int(n), int(d),
+                             1 if points_on_device else 0, _link(linkage), ctypes.byref(opt),
+                             ctypes.c_void_p(out), 1 if out_on_device else 0,
+                             ctypes.c_void_p(stream or 0), ctypes.byref(st) if stats else None)
+        _check(self.lib, rc)
+        return st.as_dict()
+
+
+_default_ctx = {}
+
+
+def _ctx(device: int) -> Context:
+    c = _default_ctx.get(device)
+    if c is None:
+        c = _default_ctx[device] = Context(device)
+    return c
+
+
+def hac_device(x, linkage, *, prune: bool = True, ctx: Context | None = None, stream=None):
+    """Cluster a CUDA (HIP) float32 tensor of shape (n, d) that lives on the GPU.
+
+    Returns ``(rows, stats)``: ``rows`` is an int64 device tensor (n-1, 4)
+    holding pc_merge records (a, b, height bits, size); ``rows[:, 2]``
+    viewed as float64 gives the heights.
+    """
+    import torch
+
+    assert x.is_cuda and x.dtype == torch.float32 and x.dim() == 2
+    x = x.contiguous()
+    n, d = x.shape
+    dev = x.device.index if x.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or _ctx(dev)
+    rows = torch.empty((max(n - 1, 1), 4), dtype=torch.int64, device=x.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+    st = ctx.hac(x.data_ptr(), n, d, linkage, rows.data_ptr(), points_on_device=True,
+                 out_on_device=True, stream=stream, prune=prune)
+    return rows[: n - 1], st
+
+
+def rows_to_Z(rows) -> np.ndarray:
+    """pc_merge records (int64 (m, 4), on host or device) -> scipy Z (float64)."""
+    import torch
+
+    r = rows.cpu() if isinstance(rows, torch.Tensor) else rows
+    r = np.ascontiguousarray(np.asarray(r, dtype=np.int64))
+    Z = np.empty((r.shape[0], 4), np.float64)
+    Z[:, 0] = r[:, 0]
+    Z[:, 1] = r[:, 1]
+    Z[:, 2] = r[:, 2].view(np.float64)
+    Z[:, 3] = r[:, 3]
+    return Z
+
+
+def hac(x, linkage, *, prune: bool = True, device: int = 0, return_stats: bool = False):
+    """Cluster points (numpy array or tensor, (n, d) float32) on the GPU.
+
+    Returns the scipy-convention linkage matrix Z (float64, (n-1, 4)).
+    """
+    import torch
+
+    if isinstance(x, torch.Tensor) and x.is_cuda:
+        xt = x.to(torch.float32)
+    else:
+        xt = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).to("cuda:%d" % device)
+    rows, st = hac_device(xt, linkage, prune=prune)
+    torch.cuda.synchronize(xt.device)
+    Z = rows_to_Z(rows)
+    return (Z, st) if return_stats else Z

@@ -1,0 +1,68 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/parchain.h declares, struct layouts match, and argument validation
+returns the documented codes before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2106_04727_amd as pc
+from paper_2106_04727_amd import parchain
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "parchain.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pc_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = pc.load_library()
+    names = header_functions()
+    assert {"pc_hac", "pc_context_create", "pc_last_error"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(parchain.EXPORTS)
+
+
+def test_struct_sizes():
+    assert ctypes.sizeof(parchain.pc_merge) == 32
+    assert ctypes.sizeof(parchain.pc_options) == 16
+    assert ctypes.sizeof(parchain.pc_stats) == 8 + 5 * 8 + 4 * 8
+
+
+def test_version_string():
+    assert "gfx950" in pc.version()
+
+
+def test_workspace_bytes_validation():
+    assert pc.workspace_bytes(0, 2, "ward") == 0
+    assert pc.workspace_bytes(10, 0, "ward") == 0
+    assert pc.workspace_bytes(10, 2, 7) == 0
+    assert pc.workspace_bytes(2**31, 2, "ward") == 0
+    a = pc.workspace_bytes(1000, 2, "ward")
+    b = pc.workspace_bytes(2000, 2, "ward")
+    assert 0 < a < b
+    # linear in n (the paper's O(n) space claim, Sec. 3 "Work and Space")
+    c = pc.workspace_bytes(4000, 2, "ward")
+    assert abs((c - b) - 2 * (b - a)) < 0.05 * (c - b)
+
+
+def test_hac_argument_checks_before_device_work():
+    lib = pc.load_library()
+    buf = (ctypes.c_float * 8)()
+    out = (parchain.pc_merge * 4)()
+    # NULL context
+    rc = lib.pc_hac(None, ctypes.cast(buf, ctypes.c_void_p), 4, 2, 0, 2, None,
+                    ctypes.cast(out, ctypes.c_void_p), 0, None, None)
+    assert rc == -1 and b"context" in lib.pc_last_error()
+    assert lib.pc_context_create(0, None) == -1
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    with pytest.raises(OSError):
+        parchain.load_library(str(tmp_path / "missing.so"))

@@ -1,0 +1,152 @@
+"""GPU parity: libparchain (through its C ABI) against the FP64 oracle.
+
+Pass criteria (on inputs the oracle certifies tie-free):
+  * identical trees (same merges, as sets of children);
+  * heights: complete and Ward are computed with the oracle's FP64 formulas
+    (inputs widened exactly, no FMA contraction), so they must agree to the
+    last bit; average sums point distances in another order, so 1e-12
+    relative (the stated contract is 1e-5);
+  * rows in the documented canonical order.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import _trees
+
+pytestmark = pytest.mark.gpu
+
+LINKS = ["complete", "average", "ward"]
+RTOL = {"complete": 0.0, "ward": 0.0, "average": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def pc():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2106_04727_amd as pc
+
+    pc.load_library()
+    return pc
+
+
+def run(pc, x, link, **kw):
+    Z, st = pc.hac(x, link, return_stats=True, **kw)
+    return Z, st
+
+
+def check_parity(pc, x, link, **kw):
+    n = x.shape[0]
+    Zo, cert = oracle.nnchain(x, link, threads=8)
+    Zg, st = run(pc, x, link, **kw)
+    _trees.assert_valid(Zg, n)
+    assert _trees.same_tree(Zg, Zo, n, rtol=RTOL[link]), (link, n, _trees.max_rel_height_err(Zg, Zo, n))
+    C = oracle.canonical(Zo, n)
+    if RTOL[link] == 0.0:
+        assert np.array_equal(Zg, C)
+    else:
+        assert np.array_equal(Zg[:, [0, 1, 3]], C[:, [0, 1, 3]]) or _trees.same_tree(Zg, C, n, rtol=1e-12)
+    return Zg, st, cert
+
+
+def test_fig1_worked_example(pc):
+    # six points shaped after the paper's worked example (Sec. 1, Fig. 1):
+    # four rounds, (a,b) and (c,d) in round 1, e's tie resolved towards {a,b}
+    x = np.array([[0.0, 3.0], [0.6, 2.2], [3.2, 0.2], [2.0, 0.0], [0.0, 0.0], [0.0, -3.0]], np.float32)
+    Zg, st, _ = check_parity(pc, x, "complete")
+    assert st["rounds"] == 4
+    Zo, _ = oracle.nnchain(x, "complete")
+    assert np.array_equal(Zg, oracle.canonical(Zo, 6))
+
+
+@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("n,d,kind,seed", [
+    (2, 2, "u", 1), (3, 2, "u", 2), (64, 2, "u", 3), (257, 1, "u", 4), (1000, 2, "b", 5),
+    (2000, 3, "u", 6), (3000, 10, "b", 7), (700, 16, "u", 8), (500, 40, "b", 9),
+])
+def test_parity_small(pc, link, n, d, kind, seed):
+    x = synth.uniform(n, d, seed) if kind == "u" else synth.blobs(n, d, 8, 0.03, seed)
+    _, cert = oracle.nnchain(x, link, threads=8)
+    if cert["min_gap"] < 1e-10:
+        pytest.skip("input not certified tie-free")
+    check_parity(pc, x, link)
+
+
+def test_parity_c1_complete_2k(pc):
+    """n=2,000 uniform points in [0,1]^2, complete linkage, seeds 0-3."""
+    for seed in range(4):
+        x = synth.uniform(2000, 2, seed)
+        check_parity(pc, x, "complete")
+
+
+@pytest.mark.parametrize("link", LINKS)
+def test_parity_blobs_20k(pc, link):
+    """Gaussian-mixture data shaped like the 1M workload, at a size the oracle
+    finishes in seconds; spans many grid rings, overflow scans and tiles."""
+    n = 20_000 if link == "ward" else 6_000
+    x = synth.blobs(n, 2, 50, 0.01, 11)
+    Zg, st, cert = check_parity(pc, x, link)
+    assert st["rounds"] > 1
+
+
+@pytest.mark.parametrize("link", LINKS)
+def test_prune_on_equals_off(pc, link):
+    x = synth.blobs(1500, 2, 6, 0.05, 21)
+    Za = pc.hac(x, link, prune=True)
+    Zb = pc.hac(x, link, prune=False)
+    assert np.array_equal(Za, Zb)
+
+
+@pytest.mark.parametrize("link", LINKS)
+def test_deterministic(pc, link):
+    x = synth.blobs(5000, 2, 20, 0.02, 22)
+    Z1 = pc.hac(x, link)
+    Z2 = pc.hac(x, link)
+    assert np.array_equal(Z1, Z2)
+
+
+def test_host_and_device_points_agree(pc):
+    import ctypes
+
+    from paper_2106_04727_amd import parchain
+
+    x = synth.blobs(3000, 2, 5, 0.05, 23)
+    Zd = pc.hac(x, "ward")
+    ctx = parchain.Context(0)
+    out = np.zeros((2999, 4), np.int64)
+    ctx.hac(x.ctypes.data, 3000, 2, "ward", out.ctypes.data, points_on_device=False,
+            out_on_device=False)
+    assert np.array_equal(parchain.rows_to_Z(out), Zd)
+
+
+def test_special_cases(pc):
+    import torch
+
+    for link in LINKS:
+        Z = pc.hac(np.zeros((1, 3), np.float32), link)
+        assert Z.shape == (0, 4)
+        Z = pc.hac(np.array([[0, 0], [3, 4]], np.float32), link)
+        assert Z.shape == (1, 4) and Z[0, 2] == 5.0 and Z[0, 3] == 2
+        x = synth.uniform(50, 2, 5)
+        x[7] = x[3]
+        Z = pc.hac(x, link)
+        assert Z[0, 2] == 0.0 and {int(Z[0, 0]), int(Z[0, 1])} == {3, 7}
+        # all points identical: every height is 0
+        Z = pc.hac(np.ones((20, 2), np.float32), link)
+        assert np.all(Z[:, 2] == 0.0)
+        _trees.assert_valid(Z, 20)
+
+
+def test_nonfinite_rejected(pc):
+    from paper_2106_04727_amd import PCError
+
+    x = synth.uniform(100, 2, 1)
+    x[5, 1] = np.nan
+    with pytest.raises(PCError) as e:
+        pc.hac(x, "ward")
+    assert e.value.status == -2
+    x[5, 1] = np.inf
+    with pytest.raises(PCError):
+        pc.hac(x, "complete")
