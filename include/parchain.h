@@ -70,7 +70,8 @@ typedef struct {
     int32_t prune;     /* 1 (default): range-query pruning (Sec. 4);
                           0: every terminal scans every active cluster
                           (same result, for ablations and tests) */
-    int32_t reserved;
+    int32_t timing;    /* 1: time the search and tile kernels with HIP events
+                          on the call's stream (fills the kernel_* stats) */
 } pc_options;
 
 /* Counters of one pc_hac call; struct_size must be sizeof(pc_stats). */
@@ -86,6 +87,10 @@ typedef struct {
     double ms_init;           /* layout + first grid */
     double ms_rounds;         /* all rounds */
     double ms_finalize;       /* sort rows + relabel */
+    /* with pc_options.timing: summed device time and launch count of the
+     * three search/evaluation kernels (HIP events around each launch) */
+    double kernel_ms[3];      /* [0] ring search, [1] full scan, [2] pair tiles */
+    int64_t kernel_launches[3];
 } pc_stats;
 
 typedef struct pc_context pc_context;

@@ -139,6 +139,7 @@ struct pc_context {
   Buf ws, pairs, tiles, part;
   Counters *hcnt = nullptr;  // pinned host mirror of the device counters
   hipEvent_t ev[4] = {};
+  hipEvent_t tev[6] = {};
   std::atomic<int> busy{0};
 };
 
@@ -162,6 +163,7 @@ pc_status pc_context_create(int device, pc_context **out) {
   c->device = dev;
   hipError_t e = hipHostMalloc((void **)&c->hcnt, sizeof(Counters), hipHostMallocDefault);
   for (int i = 0; e == hipSuccess && i < 4; ++i) e = hipEventCreate(&c->ev[i]);
+  for (int i = 0; e == hipSuccess && i < 6; ++i) e = hipEventCreate(&c->tev[i]);
   if (e != hipSuccess) {
     pc_context_destroy(c);
     return fail(PC_ERR_DEVICE, std::string("context setup: ") + hipGetErrorString(e));
@@ -182,6 +184,8 @@ void pc_context_destroy(pc_context *c) {
   if (c->hcnt) hipHostFree(c->hcnt);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) hipEventDestroy(c->ev[i]);
+  for (int i = 0; i < 6; ++i)
+    if (c->tev[i]) hipEventDestroy(c->tev[i]);
   delete c;
 }
 
@@ -274,6 +278,21 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   S.d = d;
   S.linkage = linkage;
   S.prune = prune;
+  S.timing = (opt && opt->timing) ? 1 : 0;
+  S.tev = ctx->tev;
+  double kms[3] = {0, 0, 0};
+  long long klaunch[3] = {0, 0, 0};
+  // after a synchronisation: add the timed kernels of the last round
+  auto take_times = [&]() {
+    if (!S.timing) return;
+    for (int k = 0; k < 3; ++k)
+      if (S.tlaunched[k]) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, S.tev[2 * k], S.tev[2 * k + 1]) == hipSuccess) kms[k] += ms;
+        ++klaunch[k];
+        S.tlaunched[k] = 0;
+      }
+  };
   float *xdev = (float *)points;
   if (!points_on_device) {
     xdev = xstage;
@@ -318,6 +337,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
       HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       if (h.n_pairs > S.pair_cap) {
+        S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = 0;  // the round is redone
         pc_status st = grow_pairs(ctx, S, (long long)h.n_pairs + h.n_pairs / 2 + 1024);
         if (st != PC_OK) return st;
         launch_round(S, (int)rounds, nact, s, need_pairs);
@@ -345,6 +365,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     HIPCHK(hipStreamSynchronize(s));
     if (h.nonfinite == 2) return fail(PC_ERR_DEVICE, "a terminal found no neighbour");
     if (h.nonfinite == 3) return fail(PC_ERR_DEVICE, "internal index check failed");
+    take_times();
     if (h.n_merge <= 0) return fail(PC_ERR_DEVICE, "round merged nothing");
     terms += h.n_term;
     ovfq += h.n_ovf;
@@ -376,6 +397,10 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     stats->ms_rounds = t12;
     stats->ms_finalize = t23;
     stats->ms_total = t03;
+    for (int k = 0; k < 3; ++k) {
+      stats->kernel_ms[k] = kms[k];
+      stats->kernel_launches[k] = klaunch[k];
+    }
   }
   g_err.clear();
   return PC_OK;

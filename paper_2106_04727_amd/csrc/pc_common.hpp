@@ -130,6 +130,10 @@ struct State {
   double *tile_v;
   long long pair_cap, tile_cap;
   int cell_cap;
+  // optional kernel timing: event pairs around ring search, full scan, tiles
+  int timing;
+  hipEvent_t *tev;      // 6 events (start/end per kernel), owned by the context
+  int tlaunched[3];     // kernels launched since the last read (host side)
 };
 
 // ------------------------------------------------------ launch wrappers ----

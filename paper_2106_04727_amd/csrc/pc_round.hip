@@ -77,6 +77,20 @@ __device__ __forceinline__ void count_add(long long *dst, long long v) {
   if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicAdd((unsigned long long *)dst, (unsigned long long)v);
 }
 
+// One atomic per block: reduce within each wave, then across the block's waves.
+template <class T, bool MIN>
+__device__ __forceinline__ T block_reduce(T v) {
+  __shared__ T red[kBlock / kWave];
+  v = MIN ? wave_min(v) : wave_max(v);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  T r = red[0];
+  for (int j = 1; j < kBlock / kWave; ++j) r = MIN ? (red[j] < r ? red[j] : r) : (red[j] > r ? red[j] : r);
+  return r;
+}
+
 // (value, key) lexicographic improvement test
 __device__ __forceinline__ bool better(double v, unsigned long long key, double bv, unsigned long long bkey) {
   return v < bv || (v == bv && key < bkey);
@@ -111,9 +125,10 @@ __global__ void k_point_bbox(const float *x, int n, int d, int axes, Counters *c
       lo[a] = b < lo[a] ? b : lo[a];
       hi[a] = b > hi[a] ? b : hi[a];
     }
-  for (int a = 0; a < axes; ++a) {
-    unsigned long long l = wave_min(lo[a]), h = wave_max(hi[a]);
-    if ((threadIdx.x & (kWave - 1)) == 0) {
+  for (int a = 0; a < 2; ++a) {
+    unsigned long long l = block_reduce<unsigned long long, true>(lo[a]);
+    unsigned long long h = block_reduce<unsigned long long, false>(hi[a]);
+    if (threadIdx.x == 0 && a < axes) {
       atomicMin(&c->bb_lo[a], l);
       atomicMax(&c->bb_hi[a], h);
     }
@@ -205,12 +220,12 @@ __global__ void k_act_pass(State S, int round) {
       hi[a] = b > hi[a] ? b : hi[a];
     }
   }
-  mn = wave_min(mn);
-  for (int a = 0; a < axes; ++a) {
-    lo[a] = wave_min(lo[a]);
-    hi[a] = wave_max(hi[a]);
+  mn = block_reduce<int, true>(mn);
+  for (int a = 0; a < 2; ++a) {
+    lo[a] = block_reduce<unsigned long long, true>(lo[a]);
+    hi[a] = block_reduce<unsigned long long, false>(hi[a]);
   }
-  if ((threadIdx.x & (kWave - 1)) == 0) {
+  if (threadIdx.x == 0) {
     atomicMin(&S.cnt->n_min, mn);
     for (int a = 0; a < axes; ++a) {
       atomicMin(&S.cnt->bb_lo[a], lo[a]);
@@ -1059,19 +1074,30 @@ inline int nblk(long long n, int cap = 4096) {
   return (int)(b < cap ? b : cap);
 }
 
+inline void tmark(State &S, int k, bool end, hipStream_t s) {
+  if (!S.timing) return;
+  hipEventRecord(S.tev[2 * k + (end ? 1 : 0)], s);
+  if (end) S.tlaunched[k] = 1;
+}
+
 template <int LINK>
 void launch_search(State &S, int nact, hipStream_t s, int *t_ovf) {
   const int tb = nblk(nact, 1 << 20);
+  const size_t sm = (size_t)S.d * (sizeof(double) + 2 * sizeof(float));
   if (S.d <= kGridMaxDim && S.prune) {
+    tmark(S, 0, false, s);
     if (S.d <= 2) k_nn_grid<LINK, 2, 0><<<tb, kBlock, 0, s>>>(S, t_ovf);
     else if (S.d <= 4) k_nn_grid<LINK, 4, 0><<<tb, kBlock, 0, s>>>(S, t_ovf);
     else if (S.d <= 8) k_nn_grid<LINK, 8, 0><<<tb, kBlock, 0, s>>>(S, t_ovf);
     else k_nn_grid<LINK, 16, 0><<<tb, kBlock, 0, s>>>(S, t_ovf);
-    const size_t sm = (size_t)S.d * (sizeof(double) + 2 * sizeof(float));
+    tmark(S, 0, true, s);
+    tmark(S, 1, false, s);
     k_nn_full<LINK><<<nblk((long long)nact * kBlock, 2048), kBlock, sm, s>>>(S, S.ovf, &S.cnt->n_ovf);
+    tmark(S, 1, true, s);
   } else {
-    const size_t sm = (size_t)S.d * (sizeof(double) + 2 * sizeof(float));
+    tmark(S, 1, false, s);
     k_nn_full<LINK><<<nblk((long long)nact * kBlock, 2048), kBlock, sm, s>>>(S, nullptr, nullptr);
+    tmark(S, 1, true, s);
   }
 }
 
@@ -1140,6 +1166,7 @@ void launch_pairs(State &S, int round, int npairs, long long ntiles, hipStream_t
   (void)round;
   if (npairs > 0) {
     const int tb = (int)std::min<long long>((ntiles * kWave + kBlock - 1) / kBlock, 8192);
+    tmark(S, 2, false, s);
     if (S.linkage == kComplete) {
       if (S.d <= 2) k_tiles<kComplete, 2><<<tb, kBlock, 0, s>>>(S, ntiles);
       else if (S.d <= 4) k_tiles<kComplete, 4><<<tb, kBlock, 0, s>>>(S, ntiles);
@@ -1151,6 +1178,7 @@ void launch_pairs(State &S, int round, int npairs, long long ntiles, hipStream_t
       else if (S.d <= 16) k_tiles<kAverage, 16><<<tb, kBlock, 0, s>>>(S, ntiles);
       else k_tiles<kAverage, 0><<<tb, kBlock, 0, s>>>(S, ntiles);
     }
+    tmark(S, 2, true, s);
     k_pair_finish<<<nblk((long long)npairs * kWave, 4096), kBlock, 0, s>>>(S, S.linkage);
   }
   k_term_key_reset<<<nblk(S.n, 2048), kBlock, 0, s>>>(S);

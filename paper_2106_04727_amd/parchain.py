@@ -44,7 +44,7 @@ class pc_merge(ctypes.Structure):
 
 class pc_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
-                ("prune", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("prune", ctypes.c_int32), ("timing", ctypes.c_int32)]
 
 
 class pc_stats(ctypes.Structure):
@@ -53,10 +53,17 @@ class pc_stats(ctypes.Structure):
                 ("cluster_evals", ctypes.c_int64), ("point_pair_evals", ctypes.c_int64),
                 ("overflow_queries", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("ms_init", ctypes.c_double), ("ms_rounds", ctypes.c_double),
-                ("ms_finalize", ctypes.c_double)]
+                ("ms_finalize", ctypes.c_double), ("kernel_ms", ctypes.c_double * 3),
+                ("kernel_launches", ctypes.c_int64 * 3)]
+
+    KERNELS = ("ring_search", "full_scan", "pair_tiles")
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("struct_size", "reserved")}
+        d = {k: getattr(self, k) for k, _ in self._fields_
+             if k not in ("struct_size", "reserved", "kernel_ms", "kernel_launches")}
+        d["kernels"] = {k: {"ms": self.kernel_ms[i], "launches": self.kernel_launches[i]}
+                        for i, k in enumerate(self.KERNELS)}
+        return d
 
 
 _lib = None
@@ -133,9 +140,10 @@ class Context:
             pass
 
     def hac(self, points, n: int, d: int, linkage, out, *, points_on_device: bool,
-            out_on_device: bool, stream=None, prune: bool = True, stats: bool = True):
+            out_on_device: bool, stream=None, prune: bool = True, stats: bool = True,
+            timing: bool = False):
         """Raw call: ``points``/``out`` are integer addresses."""
-        opt = pc_options(ctypes.sizeof(pc_options), 0, 1 if prune else 0, 0)
+        opt = pc_options(ctypes.sizeof(pc_options), 0, 1 if prune else 0, 1 if timing else 0)
         st = pc_stats()
         st.struct_size = ctypes.sizeof(pc_stats)
         rc = self.lib.pc_hac(self.handle, ctypes.c_void_p(points), int(n), int(d),
@@ -156,7 +164,8 @@ def _ctx(device: int) -> Context:
     return c
 
 
-def hac_device(x, linkage, *, prune: bool = True, ctx: Context | None = None, stream=None):
+def hac_device(x, linkage, *, prune: bool = True, ctx: Context | None = None, stream=None,
+               timing: bool = False):
     """Cluster a CUDA (HIP) float32 tensor of shape (n, d) that lives on the GPU.
 
     Returns ``(rows, stats)``: ``rows`` is an int64 device tensor (n-1, 4)
@@ -174,7 +183,7 @@ def hac_device(x, linkage, *, prune: bool = True, ctx: Context | None = None, st
     if stream is None:
         stream = torch.cuda.current_stream(x.device).cuda_stream
     st = ctx.hac(x.data_ptr(), n, d, linkage, rows.data_ptr(), points_on_device=True,
-                 out_on_device=True, stream=stream, prune=prune)
+                 out_on_device=True, stream=stream, prune=prune, timing=timing)
     return rows[: n - 1], st
 
 
