@@ -3,6 +3,7 @@
 // the few counter reads that size the next launches.
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -67,6 +68,10 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   S.wcen = c.take<double>(n * d);
   S.lo = c.take<float>(pts ? n * d : 1);
   S.hi = c.take<float>(pts ? n * d : 1);
+  const bool comp = linkage == kComplete;
+  S.ext = c.take<int>(comp && d <= kExtMaxDim ? n * 2 * d : 1);
+  S.crad = c.take<double>(comp ? n : 1);
+  S.sup = c.take<int>(comp && d == 2 ? n * kSupDirs : 1);
   S.act = c.take<int>(n);
   S.act2 = c.take<int>(n);
   S.term = c.take<int>(n);
@@ -78,6 +83,7 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   S.cell_cap = (int)cells;
   S.cell_cnt = c.take<int>(cells + 1);
   S.cell_start = c.take<int>(cells + 1);
+  S.cell_nmin = c.take<int>(cells + 1);
   S.cell_of = c.take<int>(n);
   S.cell_rank = c.take<int>(n);
   S.item_slot = c.take<int>(grid ? n : 1);
@@ -136,7 +142,7 @@ hipError_t grow(Buf &b, size_t bytes) {
 
 struct pc_context {
   int device = 0;
-  Buf ws, pairs, tiles, part;
+  Buf ws, pairs, tiles, part, fidx;
   Counters *hcnt = nullptr;  // pinned host mirror of the device counters
   hipEvent_t ev[4] = {};
   hipEvent_t tev[6] = {};
@@ -181,6 +187,7 @@ void pc_context_destroy(pc_context *c) {
   if (c->pairs.p) hipFree(c->pairs.p);
   if (c->tiles.p) hipFree(c->tiles.p);
   if (c->part.p) hipFree(c->part.p);
+  if (c->fidx.p) hipFree(c->fidx.p);
   if (c->hcnt) hipHostFree(c->hcnt);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) hipEventDestroy(c->ev[i]);
@@ -196,7 +203,7 @@ size_t pc_hac_workspace_bytes(int64_t n, int32_t d, int32_t linkage, const pc_op
   size_t bytes = layout(S, nullptr, n, d, linkage, true);
   if (linkage != kWard) {
     const size_t pc = (size_t)std::max<int64_t>(1 << 20, 2 * n);
-    bytes += pc * (2 * sizeof(int) + sizeof(double) + sizeof(long long)) + 1024;
+    bytes += pc * (3 * sizeof(long long) + 4 * sizeof(int)) + 1024;
     if (linkage == kAverage) bytes += ((size_t)1 << 22) * sizeof(double);
   }
   return bytes;
@@ -212,15 +219,27 @@ static pc_status grow_part(pc_context *ctx, State &S, long long longest_scan) {
 }
 
 static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
-  const size_t per = 2 * sizeof(int) + sizeof(double) + sizeof(long long);
+  // per pair: tile prefix (i64), chunk prefix (i64), value (f64), t, c, kR, kS (i32)
+  const size_t per = 3 * sizeof(long long) + 4 * sizeof(int);
   HIPCHK(grow(ctx->pairs, (size_t)cap * per + 1024));
   char *b = (char *)ctx->pairs.p;
-  S.pair_cap = (long long)((ctx->pairs.bytes - 1024) / per);
+  const long long pc = (long long)((ctx->pairs.bytes - 1024) / per);
+  S.pair_cap = pc;
   S.pr_tile0 = (long long *)b;
-  S.pr_v = (double *)(b + S.pair_cap * sizeof(long long));
-  S.pr_t = (int *)(b + S.pair_cap * (sizeof(long long) + sizeof(double)));
-  S.pr_c = S.pr_t + S.pair_cap;
+  S.pr_cbase = S.pr_tile0 + pc;
+  S.pr_v = (double *)(S.pr_cbase + pc);
+  S.pr_t = (int *)(S.pr_v + pc);
+  S.pr_c = S.pr_t + pc;
+  S.pr_kR = S.pr_c + pc;
+  S.pr_kS = S.pr_kR + pc;
   return grow_part(ctx, S, std::max<long long>(S.pair_cap, 2LL * S.n + 64));
+}
+
+static pc_status grow_fidx(pc_context *ctx, State &S, long long cap) {
+  HIPCHK(grow(ctx->fidx, (size_t)cap * sizeof(int)));
+  S.fidx = (int *)ctx->fidx.p;
+  S.fidx_cap = (long long)(ctx->fidx.bytes / sizeof(int));
+  return PC_OK;
 }
 
 static pc_status grow_tiles(pc_context *ctx, State &S, long long cap) {
@@ -280,6 +299,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   S.prune = prune;
   S.timing = (opt && opt->timing) ? 1 : 0;
   S.tev = ctx->tev;
+  S.xin = nullptr;  // set once the device copy of the points is known
   double kms[3] = {0, 0, 0};
   long long klaunch[3] = {0, 0, 0};
   // after a synchronisation: add the timed kernels of the last round
@@ -299,6 +319,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     HIPCHK(hipMemcpyAsync(xdev, points, (size_t)n * d * sizeof(float), hipMemcpyHostToDevice, s));
   }
   pc_merge *dout = out_on_device ? out : rstage;
+  S.xin = xdev;
 
   {
     pc_status st = grow_part(ctx, S, 2LL * n + 64);
@@ -308,6 +329,8 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     pc_status st = grow_pairs(ctx, S, std::max<long long>(1 << 20, 2 * n));
     if (st != PC_OK) return st;
     st = grow_tiles(ctx, S, linkage == kAverage ? (1 << 22) : 1);
+    if (st != PC_OK) return st;
+    st = grow_fidx(ctx, S, linkage == kComplete ? std::max<long long>(1 << 22, 4 * n) : 1);
     if (st != PC_OK) return st;
   }
 
@@ -324,6 +347,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(ctx->ev[1], s));
 
+  const bool debug = getenv("PC_DEBUG") != nullptr;
   int nact = (int)n;
   int merges = 0;
   long long rounds = 0, terms = 0, ovfq = 0;
@@ -351,12 +375,27 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      const long long nt = np > 0 ? h.n_tiles : 0;
-      if (linkage == kAverage && nt > S.tile_cap) {
-        pc_status st = grow_tiles(ctx, S, nt + nt / 2 + 1024);
-        if (st != PC_OK) return st;
+      long long work = 0;
+      if (linkage == kComplete) {
+        work = np > 0 ? h.n_chunks : 0;
+        if (work * kChunk > S.fidx_cap) {
+          pc_status st = grow_fidx(ctx, S, work * kChunk + work * kChunk / 2 + 1024);
+          if (st != PC_OK) return st;
+        }
+      } else {
+        work = np > 0 ? h.n_tiles : 0;
+        if (work > S.tile_cap) {
+          pc_status st = grow_tiles(ctx, S, work + work / 2 + 1024);
+          if (st != PC_OK) return st;
+        }
       }
-      launch_pairs(S, (int)rounds, np, nt, s);
+      launch_pairs(S, (int)rounds, np, work, s);
+      if (debug) {
+        HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        fprintf(stderr, "[parchain] round %lld nact %d nterm %d novf %d pairs %d work %lld tiles %lld pp %lld\n",
+                rounds, nact, h.n_term, h.n_ovf, np, work, h.n_tiles, h.point_pairs);
+      }
       HIPCHK(hipGetLastError());
     }
     launch_round_tail(S, (int)rounds, nact, merges, s);

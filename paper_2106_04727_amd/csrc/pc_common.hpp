@@ -16,6 +16,9 @@ constexpr int kMaxDim = 2048;      // largest d accepted (full-scan kernel stage
 constexpr int kGridMaxDim = 16;    // ring search over a centroid grid up to this d
 constexpr int kInlinePairs = 64;   // |t|*|C| at or below this: evaluated inside the search
 constexpr int kTile = 64;          // point-pair tile edge for deferred evaluations
+constexpr int kChunk = 256;        // points per filter block (complete linkage)
+constexpr int kExtMaxDim = 4;      // extreme-point bounds kept up to this d
+constexpr int kSupDirs = 64;       // d == 2, complete: support points in 64 fixed directions
 constexpr uint32_t kInfBits = 0x7f800000u;
 
 enum Linkage { kComplete = 0, kAverage = 1, kWard = 2 };
@@ -48,6 +51,7 @@ struct GridParams {
   double org[2];
   double h;
   double inv_h;
+  double eps;  // absolute slack for cell-boundary rounding
   int G[2];
   int ncell;
   int ncell1;  // ncell + 1 (scan length of the cell counts)
@@ -69,7 +73,7 @@ struct Counters {
   long long cluster_evals;
   long long point_pairs;
   long long n_tiles;
-  long long pad;
+  long long n_chunks;
 };
 
 // All device arrays of one clustering call. Slots are storage indices of
@@ -93,10 +97,16 @@ struct State {
   double *wsum;    // d coordinate sums per slot (FP64)
   double *wcen;    // d centroid coordinates per slot (wsum / csize)
   float *lo, *hi;  // d-dimensional bounding box per slot (complete, average)
+  int *ext;        // complete: 2d original point indices attaining the box faces (lo_k, hi_k)
+  double *crad;    // complete: upper bound of the largest centroid-to-point distance
+  int *sup;        // complete, d == 2: kSupDirs original point indices, the cluster's
+                   // support point in direction (cos, sin)(2 pi k / kSupDirs)
+  const float *xin;  // the caller's points (original order)
   // lists
   int *act, *act2, *term, *flags, *scan, *ovf;
   // grid over active centroids
   int *cell_cnt, *cell_start, *cell_of, *cell_rank;
+  int *cell_nmin;  // smallest cluster size in each cell
   int *item_slot;
   int4 *item_meta;    // (slot, size, cid, 0)
   double *item_cen;   // d per item
@@ -127,6 +137,10 @@ struct State {
   int *pr_t, *pr_c;
   double *pr_v;
   long long *pr_tile0;  // exclusive prefix of tiles per pair
+  long long *pr_cbase;  // complete: exclusive prefix of 256-point filter chunks per pair
+  int *pr_kR, *pr_kS;   // complete: points of each side kept by the filter
+  int *fidx;            // complete: kept point positions, 256-aligned region per pair
+  long long fidx_cap;
   double *tile_v;
   long long pair_cap, tile_cap;
   int cell_cap;

@@ -184,6 +184,13 @@ __global__ void k_init_slots(State S, const float *x, const unsigned *perm) {
     S.wsum[(size_t)s * d + k] = (double)v;
     S.wcen[(size_t)s * d + k] = (double)v;
   }
+  if (S.linkage == kComplete) {
+    S.crad[s] = 0.0;
+    if (d == 2)
+      for (int k = 0; k < kSupDirs; ++k) S.sup[(size_t)s * kSupDirs + k] = p;
+    if (d <= kExtMaxDim)
+      for (int k = 0; k < 2 * d; ++k) S.ext[(size_t)s * 2 * d + k] = p;
+  }
   if (S.linkage != kWard) {
     S.cbeg[s] = s;
     S.powner[s] = s;
@@ -272,6 +279,7 @@ __global__ void k_grid_params(State S, int cell_cap) {
   g.org[1] = lo[1];
   g.h = h;
   g.inv_h = 1.0 / h;
+  g.eps = 1e-13 * (fabs(lo[0]) + fabs(lo[1]) + ext[0] + ext[1] + h);
   g.G[0] = G0;
   g.G[1] = G1;
   g.ncell = G0 * G1;
@@ -289,7 +297,10 @@ __device__ __forceinline__ int cell_coord(double c, double org, double inv_h, in
 
 __global__ void k_zero_cells(State S) {
   const int nc = S.grid->ncell + 1;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) S.cell_cnt[i] = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+    S.cell_cnt[i] = 0;
+    S.cell_nmin[i] = 0x7fffffff;
+  }
 }
 
 __global__ void k_cell_count(State S) {
@@ -303,6 +314,7 @@ __global__ void k_cell_count(State S) {
     const int cell = cy * g.G[0] + cx;
     S.cell_of[i] = cell;
     S.cell_rank[i] = atomicAdd(&S.cell_cnt[cell], 1);
+    atomicMin(&S.cell_nmin[cell], S.csize[s]);
   }
 }
 
@@ -407,6 +419,96 @@ __device__ __forceinline__ void pair_bounds(const double *ct, const float *lt, c
   }
 }
 
+// ---- d == 2 support polygons (complete linkage) --------------------------
+// For unit directions u_k = (cos, sin)(2 pi k / K) a cluster keeps a point
+// s_k maximising u_k . x. The farthest pair of two clusters is attained at
+// points extreme in opposite directions, so pairs s_k(A), s_{k+K/2+j}(B) for
+// small j give a real point pair within ~(1 - cos(pi/K)) of it (lower bound).
+// The half-planes u_k . x <= u_k . s_k enclose the cluster; the farthest
+// distance from a point to the cluster is at most its farthest distance to
+// that K-gon's vertices (upper bound).
+__device__ __forceinline__ void sup_dir(int k, double &c, double &s) { sincospi(2.0 * k / kSupDirs, &s, &c); }
+
+__device__ double sup_pair_lb(const float *x, const int *sa, const int *sb) {
+  double m = 0.0;
+  for (int k = 0; k < kSupDirs; ++k) {
+    const float *pa = x + (size_t)sa[k] * 2;
+    for (int j = -2; j <= 2; ++j) {
+      const int kk = (k + kSupDirs / 2 + j + kSupDirs) % kSupDirs;
+      const float *pb = x + (size_t)sb[kk] * 2;
+      const double u = (double)pa[0] - (double)pb[0], v = (double)pa[1] - (double)pb[1];
+      const double q = u * u + v * v;
+      m = q > m ? q : m;
+    }
+  }
+  return m;
+}
+
+// vertex k of the enclosing K-gon: intersection of support lines k and k+1,
+// pushed outward by a small margin so rounding cannot shrink the polygon
+__device__ __forceinline__ void sup_vertex(const float *x, const int *sp, int k, double &vx, double &vy) {
+  const int k1 = (k + 1) % kSupDirs;
+  double c0, s0, c1, s1;
+  sup_dir(k, c0, s0);
+  sup_dir(k1, c1, s1);
+  const float *p0 = x + (size_t)sp[k] * 2, *p1 = x + (size_t)sp[k1] * 2;
+  double h0 = c0 * (double)p0[0] + s0 * (double)p0[1];
+  double h1 = c1 * (double)p1[0] + s1 * (double)p1[1];
+  h0 += 1e-12 * (fabs(h0) + 1.0);
+  h1 += 1e-12 * (fabs(h1) + 1.0);
+  const double den = c0 * s1 - s0 * c1;  // sin(2 pi / K)
+  vx = (h0 * s1 - h1 * s0) / den;
+  vy = (h1 * c0 - h0 * c1) / den;
+}
+
+// Complete linkage, pairs too large to evaluate inline: tighter bounds.
+//   comp_ub_refine: (|cA - cB| + rA + rB)^2 with rA, rB radius bounds (cheap;
+//     used while the search bound is still being lowered)
+//   comp_lb_refine: a real point pair's squared distance never exceeds the
+//     key: the farthest pair among the two clusters' extreme points
+//     (d <= kExtMaxDim) and among their opposite support points (d == 2)
+__device__ __forceinline__ void comp_ub_refine(const State &S, int t, int c, const double *ct, const double *cc,
+                                               int d, double &ub) {
+  double c2 = 0.0;
+  for (int k = 0; k < d; ++k) {
+    double u = ct[k] - cc[k];
+    c2 += u * u;
+  }
+  double us = sqrt(c2) + S.crad[t] + S.crad[c];
+  us = us * us * (1.0 + 1e-12);
+  ub = us < ub ? us : ub;
+}
+
+__device__ __forceinline__ void comp_lb_refine(const State &S, int t, int c, int d, double &lb) {
+  if (d <= kExtMaxDim) {
+    const int *et = S.ext + (size_t)t * 2 * d, *ec = S.ext + (size_t)c * 2 * d;
+    double m = 0.0;
+    for (int i = 0; i < 2 * d; ++i) {
+      const float *pa = S.xin + (size_t)et[i] * d;
+      for (int j = 0; j < 2 * d; ++j) {
+        const float *pb = S.xin + (size_t)ec[j] * d;
+        double q = 0.0;
+        for (int k = 0; k < d; ++k) {
+          double u = (double)pa[k] - (double)pb[k];
+          q += u * u;
+        }
+        m = q > m ? q : m;
+      }
+    }
+    lb = m > lb ? m : lb;
+  }
+  if (d == 2) {
+    const double m = sup_pair_lb(S.xin, S.sup + (size_t)t * kSupDirs, S.sup + (size_t)c * kSupDirs);
+    lb = m > lb ? m : lb;
+  }
+}
+
+__device__ __forceinline__ void comp_refine(const State &S, int t, int c, const double *ct, const double *cc,
+                                            int d, double &lb, double &ub) {
+  comp_lb_refine(S, t, c, d, lb);
+  comp_ub_refine(S, t, c, ct, cc, d, ub);
+}
+
 // Stop rule of the ring search: a lower bound on the key of any cluster whose
 // centroid lies at least `D` away from the terminal's centroid.
 template <int LINK>
@@ -484,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
       bool overflow = false;
       for (int k = 0; k <= kmax && !overflow; ++k) {
         if (k >= 1) {
-          const double D = ((double)(k - 1) + m) * g.h * (1.0 - 1e-9);
+          const double D = fmax(0.0, ((double)(k - 1) + m) * g.h * (1.0 - 1e-9) - g.eps);
           const double lbk = ring_key_lb<LINK>(D, nt, nmin);
           const double cur = PASS == 0 ? fmin(bound, bestv) : bound;
           if (lbk > cur) break;
@@ -549,6 +651,14 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                 const double cur = PASS == 0 ? fmin(bound, bestv) : bound;
                 if (lb > cur * kSlack) continue;
                 const long long cost = (long long)n_t * (long long)mt.y;
+                if (LINK == kComplete && cost > kInlinePairs) {
+                  if (PASS == 0) {
+                    comp_ub_refine(S, t, s, ct, cv, d, ub);
+                  } else {
+                    comp_lb_refine(S, t, s, d, lb);
+                    if (lb > cur * kSlack) continue;
+                  }
+                }
                 if (cost <= kInlinePairs) {
                   if (PASS == 0) {
                     const int beg_c = S.cbeg[s];
@@ -601,6 +711,244 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
           }
         }
       }
+    }
+  }
+  count_add(&S.cnt->cluster_evals, evals);
+  count_add(&S.cnt->point_pairs, ppairs);
+}
+
+// ------------------------------------------------ block ring search ------
+// One block per terminal handed off by the thread search. The block walks the
+// same rings; thread j takes ring cell j (row cells first, then the column
+// cells) and skips it when the cell's own lower bound -- its rectangle's
+// distance to the centroid and, for Ward, its smallest cluster size --
+// exceeds the current bound. After each ring the block agrees on the best
+// candidate and the bound, so the stop rule is uniform.
+template <int LINK>
+__device__ __forceinline__ double cell_key_lb(double D, double nt, int cnmin) {
+  if (LINK == kWard) {
+    const double nm = (double)cnmin;
+    return D * D * ((2.0 * nt * nm) / (nt + nm));
+  }
+  if (LINK == kComplete) return D * D;
+  return D;
+}
+
+template <int LINK, int MAXD>
+__global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
+  __shared__ double red_v[kBlock / kWave], red_b[kBlock / kWave];
+  __shared__ unsigned long long red_k[kBlock / kWave];
+  __shared__ double sh_bound, sh_best;
+  __shared__ unsigned long long sh_key;
+  const int count = S.cnt->n_ovf;
+  const GridParams g = *S.grid;
+  const int d = S.d;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  long long evals = 0, ppairs = 0;
+  for (int qi = blockIdx.x; qi < count; qi += gridDim.x) {
+    const int ti = S.ovf[qi];
+    const int t = S.term[ti];
+    const int cid_t = S.cid[t];
+    const int n_t = S.csize[t];
+    const double nt = (double)n_t;
+    double ct[MAXD];
+    float lt[MAXD], ht[MAXD];
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k) {
+      ct[k] = k < d ? S.wcen[(size_t)t * d + k] : 0.0;
+      lt[k] = (LINK != kWard && k < d) ? S.lo[(size_t)t * d + k] : 0.f;
+      ht[k] = (LINK != kWard && k < d) ? S.hi[(size_t)t * d + k] : 0.f;
+    }
+    const int beg_t = LINK != kWard ? S.cbeg[t] : 0;
+    const int cx = cell_coord(ct[0], g.org[0], g.inv_h, g.G[0]);
+    const int cy = g.axes == 2 ? cell_coord(ct[1], g.org[1], g.inv_h, g.G[1]) : 0;
+    const int kmax = max(max(cx, g.G[0] - 1 - cx), max(cy, g.G[1] - 1 - cy));
+    double beta_final = 0.0;
+    bool use_pred = true;
+    for (int pass = 0; pass < (LINK == kWard ? 1 : 2); ++pass) {
+      double bound = pass == 0 ? (use_pred ? beta_key<LINK>(S.predd[t]) : INFINITY) : beta_final * kSlack;
+      double bestv = INFINITY;
+      unsigned long long bestk = kNoKey;
+      double cur = bound;  // block-uniform bound
+      for (int k = 0; k <= kmax; ++k) {
+        const int ncell = k == 0 ? 1 : 8 * k;
+        for (int j0 = 0; j0 < ncell; j0 += kBlock) {
+          const int j = j0 + threadIdx.x;
+          int x = -1, y = -1;
+          if (j < ncell) {
+            if (k == 0) {
+              x = cx;
+              y = cy;
+            } else if (j < 2 * k + 1) {
+              x = cx - k + j;
+              y = cy - k;
+            } else if (j < 4 * k + 2) {
+              x = cx - k + (j - 2 * k - 1);
+              y = cy + k;
+            } else if (j < 6 * k + 1) {
+              x = cx - k;
+              y = cy - k + 1 + (j - 4 * k - 2);
+            } else {
+              x = cx + k;
+              y = cy - k + 1 + (j - 6 * k - 1);
+            }
+          }
+          if (x < 0 || y < 0 || x >= g.G[0] || y >= g.G[1]) continue;
+          const int cell = y * g.G[0] + x;
+          const int a = S.cell_start[cell], b = S.cell_start[cell + 1];
+          if (a == b) continue;
+          // distance from the centroid to this cell's rectangle
+          double dx = 0.0, dy = 0.0;
+          {
+            const double x0 = g.org[0] + x * g.h, x1 = x0 + g.h;
+            dx = ct[0] < x0 ? x0 - ct[0] : (ct[0] > x1 ? ct[0] - x1 : 0.0);
+            if (g.axes == 2) {
+              const double y0 = g.org[1] + y * g.h, y1 = y0 + g.h;
+              dy = ct[1] < y0 ? y0 - ct[1] : (ct[1] > y1 ? ct[1] - y1 : 0.0);
+            }
+          }
+          const double Dc = fmax(0.0, sqrt(dx * dx + dy * dy) * (1.0 - 1e-9) - g.eps);
+          const double mycur = pass == 0 ? fmin(cur, fmin(bound, bestv)) : cur;
+          if (cell_key_lb<LINK>(Dc, nt, S.cell_nmin[cell]) > mycur) continue;
+          for (int it = a; it < b; ++it) {
+            const int4 mt = S.item_meta[it];
+            const int sl = mt.x;
+            if (sl == t) continue;
+            const double *cc = S.item_cen + (size_t)it * d;
+            const unsigned long long key = make_key(mt.z, sl);
+            double cv[MAXD];
+#pragma unroll
+            for (int q = 0; q < MAXD; ++q) cv[q] = q < d ? cc[q] : 0.0;
+            if (LINK == kWard) {
+              const double v = ward_key<MAXD>(ct, nt, cv, (double)mt.y, d);
+              ++evals;
+              if (v <= bound && better(v, key, bestv, bestk)) {
+                bestv = v;
+                bestk = key;
+              }
+            } else {
+              float lc[MAXD], hc[MAXD];
+#pragma unroll
+              for (int q = 0; q < MAXD; ++q) {
+                lc[q] = q < d ? S.item_lo[(size_t)it * d + q] : 0.f;
+                hc[q] = q < d ? S.item_hi[(size_t)it * d + q] : 0.f;
+              }
+              double lb, ub;
+              pair_bounds<LINK, MAXD>(ct, lt, ht, cv, lc, hc, d, lb, ub);
+              const double c2 = pass == 0 ? fmin(cur, fmin(bound, bestv)) : cur;
+              if (lb > c2 * kSlack) continue;
+              const long long cost = (long long)n_t * (long long)mt.y;
+              if (LINK == kComplete && cost > kInlinePairs) {
+                if (pass == 0) {
+                  comp_ub_refine(S, t, sl, ct, cv, d, ub);
+                } else {
+                  comp_lb_refine(S, t, sl, d, lb);
+                  if (lb > c2 * kSlack) continue;
+                }
+              }
+              if (cost <= kInlinePairs) {
+                if (pass == 0) {
+                  const int beg_c = S.cbeg[sl];
+                  const double v = (mt.z < cid_t) ? pair_exact_inline<LINK>(S.px, d, beg_c, mt.y, beg_t, n_t)
+                                                  : pair_exact_inline<LINK>(S.px, d, beg_t, n_t, beg_c, mt.y);
+                  ++evals;
+                  ppairs += cost;
+                  if (better(v, key, bestv, bestk)) {
+                    bestv = v;
+                    bestk = key;
+                  }
+                }
+              } else if (pass == 0) {
+                if (ub < bound) bound = ub;
+              } else {
+                const int pp = atomicAdd(&S.cnt->n_pairs, 1);
+                if (pp < S.pair_cap) {
+                  S.pr_t[pp] = ti;
+                  S.pr_c[pp] = sl;
+                } else {
+                  S.cnt->pair_overflow = 1;
+                }
+              }
+            }
+          }
+        }
+        if (pass == 0) {
+          // agree on the best candidate and the bound
+          double bv = bestv, bb = bound;
+          unsigned long long bk = bestk;
+          for (int o = kWave / 2; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o, kWave), ob = __shfl_xor(bb, o, kWave);
+            const unsigned long long ok = __shfl_xor(bk, o, kWave);
+            if (better(ov, ok, bv, bk)) {
+              bv = ov;
+              bk = ok;
+            }
+            bb = fmin(bb, ob);
+          }
+          if (lane == 0) {
+            red_v[wv] = bv;
+            red_k[wv] = bk;
+            red_b[wv] = bb;
+          }
+          __syncthreads();
+          if (threadIdx.x == 0) {
+            double v0 = red_v[0], b0 = red_b[0];
+            unsigned long long k0 = red_k[0];
+            for (int q = 1; q < kBlock / kWave; ++q) {
+              if (better(red_v[q], red_k[q], v0, k0)) {
+                v0 = red_v[q];
+                k0 = red_k[q];
+              }
+              b0 = fmin(b0, red_b[q]);
+            }
+            sh_best = v0;
+            sh_key = k0;
+            sh_bound = b0;
+          }
+          __syncthreads();
+          bestv = sh_best;
+          bestk = sh_key;
+          bound = sh_bound;
+          cur = fmin(bound, bestv);
+          __syncthreads();
+        }
+        // stop when the next ring cannot hold anything better
+        if (k + 1 <= kmax) {
+          double m = 0.5;
+          {
+            double f = (ct[0] - g.org[0]) * g.inv_h - (double)cx;
+            f = f < 0 ? 0 : (f > 1 ? 1 : f);
+            m = fmin(m, fmin(f, 1.0 - f));
+            if (g.axes == 2) {
+              double f1 = (ct[1] - g.org[1]) * g.inv_h - (double)cy;
+              f1 = f1 < 0 ? 0 : (f1 > 1 ? 1 : f1);
+              m = fmin(m, fmin(f1, 1.0 - f1));
+            }
+          }
+          const double D = fmax(0.0, ((double)k + m) * g.h * (1.0 - 1e-9) - g.eps);
+          if (ring_key_lb<LINK>(D, nt, (double)S.cnt->n_min) > cur) break;
+        }
+      }
+      if (LINK == kWard && pass == 0 && bestk == kNoKey && use_pred) {
+        // the predecessor bound held nothing (cannot happen for an exact
+        // bound): search again without it
+        use_pred = false;
+        pass = -1;
+        __syncthreads();
+        continue;
+      }
+      if (pass == 0) {
+        beta_final = fmin(bound, bestv);
+        if (threadIdx.x == 0) {
+          S.t_best[ti] = bestv;
+          S.t_key[ti] = bestk;
+          if (LINK != kWard) {
+            S.t_beta[ti] = beta_final;
+            S.t_min[ti] = pos_bits(bestv);
+          }
+        }
+      }
+      __syncthreads();
     }
   }
   count_add(&S.cnt->cluster_evals, evals);
@@ -660,6 +1008,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
         pair_bounds<LINK, 0>(ct, lt, ht, cc, S.lo + (size_t)s * d, S.hi + (size_t)s * d, d, lb, ub);
         if (S.prune && lb > fmin(bound, bestv) * kSlack) continue;
         const long long cost = (long long)n_t * n_c;
+        if (LINK == kComplete && cost > kInlinePairs) comp_ub_refine(S, t, s, ct, cc, d, ub);
         if (cost <= kInlinePairs) {
           const int beg_c = S.cbeg[s];
           const double v = (S.cid[s] < cid_t) ? pair_exact_inline<LINK>(S.px, d, beg_c, n_c, beg_t, n_t)
@@ -726,6 +1075,10 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
           pair_bounds<LINK, 0>(ct, lt, ht, S.wcen + (size_t)s * d, S.lo + (size_t)s * d, S.hi + (size_t)s * d,
                                d, lb, ub);
           if (lb > beta * kSlack) continue;
+          if (LINK == kComplete) {
+            comp_lb_refine(S, t, s, d, lb);
+            if (lb > beta * kSlack) continue;
+          }
         }
         const int p = atomicAdd(&S.cnt->n_pairs, 1);
         if (p < S.pair_cap) {
@@ -764,73 +1117,280 @@ __global__ void k_pair_tiles(State S, long long *ntl) {
   }
 }
 
-// One wavefront per 64x64 tile: lane j owns column point j of the pair's S
-// side and walks the tile's R rows (row points are wave-uniform loads).
-template <int LINK, int MAXD>
-__global__ __launch_bounds__(kBlock) void k_tiles(State S, long long ntiles) {
+// Average linkage: one wavefront per 64x64 tile of a pair's point ranges,
+// rows = the cluster with the lower ID. Rows are staged in LDS as FP64; lane
+// j owns column point j; the tile's FP64 sum of point distances goes to
+// tile_v[tile] and is added up per pair in a fixed order later.
+template <int MAXD>
+__global__ __launch_bounds__(kBlock) void k_tiles_avg(State S, long long ntiles) {
+  constexpr int kW = kBlock / kWave;
+  constexpr int MD = MAXD > 0 ? MAXD : 1;
+  __shared__ double rows[kW][kTile][MD];
   const int np = S.cnt->n_pairs;
-  const int lane = threadIdx.x & (kWave - 1);
-  const long long wave0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const long long nwaves = ((long long)gridDim.x * blockDim.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int d = S.d;
   long long ppairs = 0;
-  for (long long gt = wave0; gt < ntiles; gt += nwaves) {
-    // pair of this tile: last p with pr_tile0[p] <= gt
-    int lo = 0, hi = np - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (S.pr_tile0[mid] <= gt) lo = mid;
-      else hi = mid - 1;
+  const long long ngroups = (ntiles + kW - 1) / kW;
+  for (long long gg = blockIdx.x; gg < ngroups; gg += gridDim.x) {
+    const long long gt = gg * kW + w;
+    const bool active = gt < ntiles;
+    int br = 0, r0 = 0, nrow = 0, col = 0, ns = 0, bs = 0;
+    if (active) {
+      int lo = 0, hi = np - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (S.pr_tile0[mid] <= gt) lo = mid;
+        else hi = mid - 1;
+      }
+      const int p = lo;
+      int nr;
+      pair_orient(S, p, br, nr, bs, ns);
+      const long long local = gt - S.pr_tile0[p];
+      const int ntc = (ns + kTile - 1) / kTile;
+      const int rt = (int)(local / ntc), ctl = (int)(local % ntc);
+      r0 = rt * kTile;
+      nrow = min(nr, r0 + kTile) - r0;
+      col = ctl * kTile + lane;
     }
-    const int p = lo;
-    int br, nr, bs, ns;
-    pair_orient(S, p, br, nr, bs, ns);
-    const long long local = gt - S.pr_tile0[p];
-    const int ntc = (ns + kTile - 1) / kTile;
-    const int rt = (int)(local / ntc), ctl = (int)(local % ntc);
-    const int r0 = rt * kTile, r1 = min(nr, r0 + kTile);
-    const int col = ctl * kTile + lane;
-    const bool valid = col < ns;
+    __syncthreads();
+    if (MAXD > 0 && active && lane < nrow) {
+      const float *pr = S.px + (size_t)(br + r0 + lane) * d;
+#pragma unroll
+      for (int k = 0; k < MD; ++k) rows[w][lane][k] = k < d ? (double)pr[k] : 0.0;
+    }
+    __syncthreads();
     double acc = 0.0;
-    if (valid) {
+    if (active && col < ns) {
       const float *pc = S.px + (size_t)(bs + col) * d;
       if (MAXD > 0) {
-        double cv[MAXD > 0 ? MAXD : 1];
+        double cv[MD];
 #pragma unroll
-        for (int k = 0; k < MAXD; ++k) cv[k] = k < d ? (double)pc[k] : 0.0;
-        for (int r = r0; r < r1; ++r) {
-          const float *pr = S.px + (size_t)(br + r) * d;
-          double q = 0.0;
+        for (int k = 0; k < MD; ++k) cv[k] = k < d ? (double)pc[k] : 0.0;
+        for (int rr = 0; rr < nrow; ++rr) {
+          double qd = 0.0;
 #pragma unroll
-          for (int k = 0; k < MAXD; ++k)
+          for (int k = 0; k < MD; ++k)
             if (k < d) {
-              double t = (double)pr[k] - cv[k];
-              q += t * t;
+              double u = rows[w][rr][k] - cv[k];
+              qd += u * u;
             }
-          if (LINK == kComplete) acc = q > acc ? q : acc;
-          else acc += sqrt(q);
+          acc += sqrt(qd);
         }
       } else {
-        for (int r = r0; r < r1; ++r) {
-          const float *pr = S.px + (size_t)(br + r) * d;
-          double q = 0.0;
+        for (int rr = 0; rr < nrow; ++rr) {
+          const float *pr = S.px + (size_t)(br + r0 + rr) * d;
+          double qd = 0.0;
           for (int k = 0; k < d; ++k) {
-            double t = (double)pr[k] - (double)pc[k];
-            q += t * t;
+            double u = (double)pr[k] - (double)pc[k];
+            qd += u * u;
           }
-          if (LINK == kComplete) acc = q > acc ? q : acc;
-          else acc += sqrt(q);
+          acc += sqrt(qd);
         }
       }
-      ppairs += r1 - r0;
+      ppairs += nrow;
     }
-    if (LINK == kComplete) {
-      acc = wave_max(acc);
-      if (lane == 0) atomicMax((unsigned long long *)&S.pr_v[p], pos_bits(acc));
-    } else {
-      acc = wave_sum(acc);
-      if (lane == 0) S.tile_v[gt] = acc;
+    acc = wave_sum(acc);
+    if (active && lane == 0) S.tile_v[gt] = acc;
+  }
+  count_add(&S.cnt->point_pairs, ppairs);
+}
+
+// ---- complete linkage: exact pruning inside a pair -----------------------
+// With L a lower bound of the pair's key, only a point whose farthest possible
+// distance to the other cluster exceeds L can end the farthest pair; the key is
+// max(L, max over the kept points' pairs). The farthest pair itself is always
+// kept, and if nothing is kept the key is L.
+__device__ __forceinline__ void pair_slots(const State &S, int p, int &r, int &q) {
+  const int t = S.term[S.pr_t[p]];
+  const int c = S.pr_c[p];
+  const bool tlow = S.cid[t] < S.cid[c];
+  r = tlow ? t : c;
+  q = tlow ? c : t;
+}
+
+__global__ void k_pair_prep_comp(State S, long long *nch) {
+  const int np = S.cnt->n_pairs;
+  const int d = S.d;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+    int r, q;
+    pair_slots(S, p, r, q);
+    const double *cr = S.wcen + (size_t)r * d, *cq = S.wcen + (size_t)q * d;
+    double lb, ub;
+    pair_bounds<kComplete, 0>(cr, S.lo + (size_t)r * d, S.hi + (size_t)r * d, cq, S.lo + (size_t)q * d,
+                              S.hi + (size_t)q * d, d, lb, ub);
+    comp_refine(S, r, q, cr, cq, d, lb, ub);
+    S.pr_v[p] = lb;
+    S.pr_kR[p] = 0;
+    S.pr_kS[p] = 0;
+    nch[p] = (S.csize[r] + S.csize[q] + kChunk - 1) / kChunk;
+  }
+}
+
+// squared farthest-distance bound from a point to a cluster: min of the box
+// corner bound and (|x - c| + radius)^2
+__device__ __forceinline__ double point_far_ub(const float *x, const State &S, int c, int d) {
+  const float *lo = S.lo + (size_t)c * d, *hi = S.hi + (size_t)c * d;
+  const double *cc = S.wcen + (size_t)c * d;
+  double box = 0.0, c2 = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double v = (double)x[k];
+    const double a = v - (double)lo[k], b = (double)hi[k] - v;
+    const double e = a > b ? a : b;
+    box += e * e;
+    const double u = v - cc[k];
+    c2 += u * u;
+  }
+  double sp = sqrt(c2) + S.crad[c];
+  sp = sp * sp;
+  return (box < sp ? box : sp) * (1.0 + 1e-12);
+}
+
+// one block per 256-point chunk of a pair's points (both sides)
+__global__ __launch_bounds__(kBlock) void k_filter_comp(State S, long long nchunks) {
+  __shared__ int sp;
+  __shared__ double vtx[2][kSupDirs][2];  // enclosing polygons of R (0) and S (1), d == 2
+  const int np = S.cnt->n_pairs;
+  const int d = S.d;
+  for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    if (threadIdx.x == 0) {
+      int lo = 0, hi = np - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (S.pr_cbase[mid] <= ch) lo = mid;
+        else hi = mid - 1;
+      }
+      sp = lo;
     }
+    __syncthreads();
+    const int p = sp;
+    int r, q;
+    pair_slots(S, p, r, q);
+    if (d == 2 && threadIdx.x < 2 * kSupDirs) {
+      const int side = threadIdx.x / kSupDirs, k = threadIdx.x % kSupDirs;
+      double vx, vy;
+      sup_vertex(S.xin, S.sup + (size_t)(side ? q : r) * kSupDirs, k, vx, vy);
+      vtx[side][k][0] = vx;
+      vtx[side][k][1] = vy;
+    }
+    __syncthreads();
+    const int nR = S.csize[r], nS = S.csize[q];
+    const long long region = S.pr_cbase[p] * kChunk;
+    const int local = (int)((ch - S.pr_cbase[p]) * kChunk) + threadIdx.x;
+    if (local < nR + nS) {
+      const bool rside = local < nR;
+      const int pos = rside ? S.cbeg[r] + local : S.cbeg[q] + (local - nR);
+      const float *xp = S.px + (size_t)pos * d;
+      double ub = point_far_ub(xp, S, rside ? q : r, d);
+      if (d == 2 && ub >= S.pr_v[p]) {
+        // farthest distance to the other cluster's enclosing polygon
+        const int side = rside ? 1 : 0;
+        const double px0 = (double)xp[0], px1 = (double)xp[1];
+        double m = 0.0;
+        for (int k = 0; k < kSupDirs; ++k) {
+          const double u = px0 - vtx[side][k][0], v = px1 - vtx[side][k][1];
+          const double qd = u * u + v * v;
+          m = qd > m ? qd : m;
+        }
+        m *= 1.0 + 1e-10;
+        ub = m < ub ? m : ub;
+      }
+      if (ub >= S.pr_v[p]) {
+        const int k = atomicAdd(rside ? &S.pr_kR[p] : &S.pr_kS[p], 1);
+        S.fidx[region + (rside ? 0 : nR) + k] = pos;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_pair_tiles_f(State S, long long *ntl) {
+  const int np = S.cnt->n_pairs;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+    const int kr = S.pr_kR[p], ks = S.pr_kS[p];
+    ntl[p] = (long long)((kr + kTile - 1) / kTile) * (long long)((ks + kTile - 1) / kTile);
+  }
+}
+
+// Tiles of kept points. A block takes four consecutive tiles per step (one per
+// wavefront; the loop bound is uniform over the block so barriers are safe).
+// Each wavefront stages its tile's 64 row points in LDS as FP64; lane j owns
+// kept column point j and sweeps the rows with broadcast LDS reads.
+template <int MAXD>
+__global__ __launch_bounds__(kBlock) void k_tiles_comp(State S) {
+  constexpr int kW = kBlock / kWave;
+  constexpr int MD = MAXD > 0 ? MAXD : 1;
+  __shared__ double rows[kW][kTile][MD];
+  const int np = S.cnt->n_pairs;
+  const long long ntiles = S.cnt->n_tiles;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int d = S.d;
+  long long ppairs = 0;
+  const long long ngroups = (ntiles + kW - 1) / kW;
+  for (long long gg = blockIdx.x; gg < ngroups; gg += gridDim.x) {
+    const long long gt = gg * kW + w;
+    const bool active = gt < ntiles;
+    int p = 0, r0 = 0, nrow = 0, col = 0, ks = 0, nR = 0;
+    long long region = 0;
+    if (active) {
+      int lo = 0, hi = np - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (S.pr_tile0[mid] <= gt) lo = mid;
+        else hi = mid - 1;
+      }
+      p = lo;
+      int r, q;
+      pair_slots(S, p, r, q);
+      nR = S.csize[r];
+      const int kr = S.pr_kR[p];
+      ks = S.pr_kS[p];
+      region = S.pr_cbase[p] * kChunk;
+      const long long local = gt - S.pr_tile0[p];
+      const int ntc = (ks + kTile - 1) / kTile;
+      const int rt = (int)(local / ntc), ctl = (int)(local % ntc);
+      r0 = rt * kTile;
+      nrow = min(kr, r0 + kTile) - r0;
+      col = ctl * kTile + lane;
+    }
+    __syncthreads();
+    if (MAXD > 0 && active && lane < nrow) {
+      const float *pr = S.px + (size_t)S.fidx[region + r0 + lane] * d;
+#pragma unroll
+      for (int k = 0; k < MD; ++k) rows[w][lane][k] = k < d ? (double)pr[k] : 0.0;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    if (active && col < ks) {
+      const float *pc = S.px + (size_t)S.fidx[region + nR + col] * d;
+      if (MAXD > 0) {
+        double cv[MD];
+#pragma unroll
+        for (int k = 0; k < MD; ++k) cv[k] = k < d ? (double)pc[k] : 0.0;
+        for (int rr = 0; rr < nrow; ++rr) {
+          double qd = 0.0;
+#pragma unroll
+          for (int k = 0; k < MD; ++k)
+            if (k < d) {
+              double u = rows[w][rr][k] - cv[k];
+              qd += u * u;
+            }
+          acc = qd > acc ? qd : acc;
+        }
+      } else {
+        for (int rr = 0; rr < nrow; ++rr) {
+          const float *pr = S.px + (size_t)S.fidx[region + r0 + rr] * d;
+          double qd = 0.0;
+          for (int k = 0; k < d; ++k) {
+            double u = (double)pr[k] - (double)pc[k];
+            qd += u * u;
+          }
+          acc = qd > acc ? qd : acc;
+        }
+      }
+      ppairs += nrow;
+    }
+    acc = wave_max(acc);
+    if (active && lane == 0) atomicMax((unsigned long long *)&S.pr_v[p], pos_bits(acc));
   }
   count_add(&S.cnt->point_pairs, ppairs);
 }
@@ -962,6 +1522,37 @@ __global__ void k_merge(State S, int base) {
     S.eff[a] = e;
     const int ns = sa + sb;
     S.csize[a] = ns;
+    if (S.linkage == kComplete) {
+      // radius bound of the union: max over children of |c_new - c_child| + r_child
+      // (old centroids are still in place here)
+      double da = 0.0, db = 0.0;
+      for (int k = 0; k < d; ++k) {
+        const double c = (S.wsum[(size_t)a * d + k] + S.wsum[(size_t)b * d + k]) / (double)ns;
+        const double ta = c - S.wcen[(size_t)a * d + k], tb = c - S.wcen[(size_t)b * d + k];
+        da += ta * ta;
+        db += tb * tb;
+      }
+      const double ra = sqrt(da) + S.crad[a], rb = sqrt(db) + S.crad[b];
+      S.crad[a] = (ra > rb ? ra : rb) * (1.0 + 1e-12);
+      if (d == 2)
+        for (int k = 0; k < kSupDirs; ++k) {
+          int *sa = S.sup + (size_t)a * kSupDirs + k;
+          const int sb = S.sup[(size_t)b * kSupDirs + k];
+          double c, sn;
+          sup_dir(k, c, sn);
+          const float *pa = S.xin + (size_t)(*sa) * 2, *pb = S.xin + (size_t)sb * 2;
+          const double va = c * (double)pa[0] + sn * (double)pa[1], vb = c * (double)pb[0] + sn * (double)pb[1];
+          if (vb > va || (vb == va && sb < *sa)) *sa = sb;
+        }
+      if (d <= kExtMaxDim)
+        for (int k = 0; k < d; ++k) {
+          int *ea = S.ext + (size_t)a * 2 * d, *eb = S.ext + (size_t)b * 2 * d;
+          const float la = S.xin[(size_t)ea[2 * k] * d + k], lb = S.xin[(size_t)eb[2 * k] * d + k];
+          if (lb < la || (lb == la && eb[2 * k] < ea[2 * k])) ea[2 * k] = eb[2 * k];
+          const float ha = S.xin[(size_t)ea[2 * k + 1] * d + k], hb = S.xin[(size_t)eb[2 * k + 1] * d + k];
+          if (hb > ha || (hb == ha && eb[2 * k + 1] < ea[2 * k + 1])) ea[2 * k + 1] = eb[2 * k + 1];
+        }
+    }
     for (int k = 0; k < d; ++k) {
       const double sum = S.wsum[(size_t)a * d + k] + S.wsum[(size_t)b * d + k];
       S.wsum[(size_t)a * d + k] = sum;
@@ -1092,7 +1683,11 @@ void launch_search(State &S, int nact, hipStream_t s, int *t_ovf) {
     else k_nn_grid<LINK, 16, 0><<<tb, kBlock, 0, s>>>(S, t_ovf);
     tmark(S, 0, true, s);
     tmark(S, 1, false, s);
-    k_nn_full<LINK><<<nblk((long long)nact * kBlock, 2048), kBlock, sm, s>>>(S, S.ovf, &S.cnt->n_ovf);
+    const int ob = nblk((long long)nact * kBlock, 2048);
+    if (S.d <= 2) k_nn_ringblk<LINK, 2><<<ob, kBlock, 0, s>>>(S);
+    else if (S.d <= 4) k_nn_ringblk<LINK, 4><<<ob, kBlock, 0, s>>>(S);
+    else if (S.d <= 8) k_nn_ringblk<LINK, 8><<<ob, kBlock, 0, s>>>(S);
+    else k_nn_ringblk<LINK, 16><<<ob, kBlock, 0, s>>>(S);
     tmark(S, 1, true, s);
   } else {
     tmark(S, 1, false, s);
@@ -1156,29 +1751,40 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
 }
 
 void launch_pairs_prefix(State &S, int npairs, hipStream_t s) {
-  long long *ntl = (long long *)S.pr_tile0;
-  // per-pair tile counts, then their exclusive prefix (in place)
-  k_pair_tiles<<<nblk(npairs, 2048), kBlock, 0, s>>>(S, ntl);
-  scan_exclusive_i64(ntl, S.pr_tile0, npairs, &S.cnt->n_pairs, &S.cnt->n_tiles, S.part, s);
+  long long *tmp = S.pr_tile0;  // per-pair counts, then their exclusive prefix (in place)
+  if (S.linkage == kComplete) {
+    k_pair_prep_comp<<<nblk(npairs, 2048), kBlock, 0, s>>>(S, S.pr_cbase);
+    scan_exclusive_i64(S.pr_cbase, S.pr_cbase, npairs, &S.cnt->n_pairs, &S.cnt->n_chunks, S.part, s);
+  } else {
+    k_pair_tiles<<<nblk(npairs, 2048), kBlock, 0, s>>>(S, tmp);
+    scan_exclusive_i64(tmp, S.pr_tile0, npairs, &S.cnt->n_pairs, &S.cnt->n_tiles, S.part, s);
+  }
 }
 
-void launch_pairs(State &S, int round, int npairs, long long ntiles, hipStream_t s) {
+// complete: `work` = filter chunks; average: `work` = tiles
+void launch_pairs(State &S, int round, int npairs, long long work, hipStream_t s) {
   (void)round;
   if (npairs > 0) {
-    const int tb = (int)std::min<long long>((ntiles * kWave + kBlock - 1) / kBlock, 8192);
-    tmark(S, 2, false, s);
     if (S.linkage == kComplete) {
-      if (S.d <= 2) k_tiles<kComplete, 2><<<tb, kBlock, 0, s>>>(S, ntiles);
-      else if (S.d <= 4) k_tiles<kComplete, 4><<<tb, kBlock, 0, s>>>(S, ntiles);
-      else if (S.d <= 16) k_tiles<kComplete, 16><<<tb, kBlock, 0, s>>>(S, ntiles);
-      else k_tiles<kComplete, 0><<<tb, kBlock, 0, s>>>(S, ntiles);
+      k_filter_comp<<<(int)std::min<long long>(work, 1 << 20), kBlock, 0, s>>>(S, work);
+      k_pair_tiles_f<<<nblk(npairs, 2048), kBlock, 0, s>>>(S, S.pr_tile0);
+      scan_exclusive_i64(S.pr_tile0, S.pr_tile0, npairs, &S.cnt->n_pairs, &S.cnt->n_tiles, S.part, s);
+      tmark(S, 2, false, s);
+      if (S.d <= 2) k_tiles_comp<2><<<2048, kBlock, 0, s>>>(S);
+      else if (S.d <= 4) k_tiles_comp<4><<<2048, kBlock, 0, s>>>(S);
+      else if (S.d <= 16) k_tiles_comp<16><<<2048, kBlock, 0, s>>>(S);
+      else k_tiles_comp<0><<<2048, kBlock, 0, s>>>(S);
+      tmark(S, 2, true, s);
     } else {
-      if (S.d <= 2) k_tiles<kAverage, 2><<<tb, kBlock, 0, s>>>(S, ntiles);
-      else if (S.d <= 4) k_tiles<kAverage, 4><<<tb, kBlock, 0, s>>>(S, ntiles);
-      else if (S.d <= 16) k_tiles<kAverage, 16><<<tb, kBlock, 0, s>>>(S, ntiles);
-      else k_tiles<kAverage, 0><<<tb, kBlock, 0, s>>>(S, ntiles);
+      const long long ntiles = work;
+      const int tb = (int)std::min<long long>((ntiles * kWave + kBlock - 1) / kBlock, 8192);
+      tmark(S, 2, false, s);
+      if (S.d <= 2) k_tiles_avg<2><<<tb, kBlock, 0, s>>>(S, ntiles);
+      else if (S.d <= 4) k_tiles_avg<4><<<tb, kBlock, 0, s>>>(S, ntiles);
+      else if (S.d <= 16) k_tiles_avg<16><<<tb, kBlock, 0, s>>>(S, ntiles);
+      else k_tiles_avg<0><<<tb, kBlock, 0, s>>>(S, ntiles);
+      tmark(S, 2, true, s);
     }
-    tmark(S, 2, true, s);
     k_pair_finish<<<nblk((long long)npairs * kWave, 4096), kBlock, 0, s>>>(S, S.linkage);
   }
   k_term_key_reset<<<nblk(S.n, 2048), kBlock, 0, s>>>(S);
