@@ -29,9 +29,19 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_VEC_TFLOPS = 78.6
 
-# Algorithmic unit costs (one linkage-distance evaluation / one point pair).
-WARD_EVAL_BYTES = 32       # candidate centroid (2 x f64) + (slot, size, cid, pad) record
-COMPLETE_PAIR_FLOPS = 6    # 2 sub, 2 mul, 1 add, 1 max per point pair at d = 2 (FP64)
+# Algorithmic unit costs.
+#   search kernels: per candidate visited, its 16-byte (slot, size, cid) record
+#   and FP64 centroid (8 d bytes), plus the float32 box (8 d bytes) for
+#   complete/average; the kernels are gathers, so they are priced against HBM
+#   bandwidth.
+#   complete tiles: 6 FP64 flops per point pair at d = 2 (2 sub, 2 mul, 1 add,
+#   1 max), priced against the FP64 vector peak.
+def visit_bytes(link, d=2):
+    return 16 + 8 * d + (0 if link == "ward" else 8 * d)
+
+
+COMPLETE_PAIR_FLOPS = 6
+KERNEL_NAMES = ("ring_search", "block_search", "pair_tiles", "ring_emit")
 
 LINKS = ("ward", "complete")
 
@@ -108,12 +118,12 @@ def main():
     # dominant kernel over the step (largest summed event time)
     cands = []
     for link, sts in per.items():
-        for kname in ("ring_search", "full_scan", "pair_tiles"):
+        for kname in KERNEL_NAMES:
             ms = sum(s["kernels"][kname]["ms"] for s in sts)
             nl = sum(s["kernels"][kname]["launches"] for s in sts)
             if nl:
                 cands.append((ms, link, kname, nl, sts))
-    cands.sort(reverse=True)
+    cands.sort(key=lambda c: c[0], reverse=True)
     roof = None
     if cands:
         ms, link, kname, nl, sts = cands[0]
@@ -124,12 +134,13 @@ def main():
             roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VEC_TFLOPS,
                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VEC_TFLOPS, "traffic": None}
         else:
-            work = sum(s["cluster_evals"] for s in sts) * WARD_EVAL_BYTES / nl
+            work = sum(s["kernels"][kname]["visits"] for s in sts) * visit_bytes(link) / nl
             achieved = work / (avg_ms / 1000.0) / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None}
         roof.update({"kernel": kname, "linkage": link, "avg_launch_ms": avg_ms, "launches": nl,
-                     "work_per_launch": work})
+                     "work_per_launch": work,
+                     "note": "search kernels gather candidate records; work = visits x record bytes"})
 
     value = n * len(links) / (wall / max(args.steps, 1))
     out = {

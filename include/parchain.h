@@ -88,9 +88,12 @@ typedef struct {
     double ms_rounds;         /* all rounds */
     double ms_finalize;       /* sort rows + relabel */
     /* with pc_options.timing: summed device time and launch count of the
-     * three search/evaluation kernels (HIP events around each launch) */
-    double kernel_ms[3];      /* [0] ring search, [1] full scan, [2] pair tiles */
-    int64_t kernel_launches[3];
+     * search/evaluation kernels (HIP events around each launch) */
+    double kernel_ms[4];      /* [0] ring search (bound pass), [1] block ring
+                                 search / full scan, [2] pair tiles,
+                                 [3] ring search (pair emission pass) */
+    int64_t kernel_launches[4];
+    int64_t candidate_visits[4]; /* candidate clusters examined, per kernel above */
 } pc_stats;
 
 typedef struct pc_context pc_context;

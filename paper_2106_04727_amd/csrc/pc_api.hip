@@ -142,10 +142,10 @@ hipError_t grow(Buf &b, size_t bytes) {
 
 struct pc_context {
   int device = 0;
-  Buf ws, pairs, tiles, part, fidx;
+  Buf ws, pairs, tiles, part, fidx, cand;
   Counters *hcnt = nullptr;  // pinned host mirror of the device counters
   hipEvent_t ev[4] = {};
-  hipEvent_t tev[6] = {};
+  hipEvent_t tev[8] = {};
   std::atomic<int> busy{0};
 };
 
@@ -167,9 +167,10 @@ pc_status pc_context_create(int device, pc_context **out) {
   pc_context *c = new (std::nothrow) pc_context();
   if (!c) return fail(PC_ERR_OUT_OF_MEMORY, "host allocation failed");
   c->device = dev;
-  hipError_t e = hipHostMalloc((void **)&c->hcnt, sizeof(Counters), hipHostMallocDefault);
+  hipError_t e = set_direction_table();
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->hcnt, sizeof(Counters), hipHostMallocDefault);
   for (int i = 0; e == hipSuccess && i < 4; ++i) e = hipEventCreate(&c->ev[i]);
-  for (int i = 0; e == hipSuccess && i < 6; ++i) e = hipEventCreate(&c->tev[i]);
+  for (int i = 0; e == hipSuccess && i < 8; ++i) e = hipEventCreate(&c->tev[i]);
   if (e != hipSuccess) {
     pc_context_destroy(c);
     return fail(PC_ERR_DEVICE, std::string("context setup: ") + hipGetErrorString(e));
@@ -188,10 +189,11 @@ void pc_context_destroy(pc_context *c) {
   if (c->tiles.p) hipFree(c->tiles.p);
   if (c->part.p) hipFree(c->part.p);
   if (c->fidx.p) hipFree(c->fidx.p);
+  if (c->cand.p) hipFree(c->cand.p);
   if (c->hcnt) hipHostFree(c->hcnt);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) hipEventDestroy(c->ev[i]);
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 8; ++i)
     if (c->tev[i]) hipEventDestroy(c->tev[i]);
   delete c;
 }
@@ -249,6 +251,17 @@ static pc_status grow_tiles(pc_context *ctx, State &S, long long cap) {
   return PC_OK;
 }
 
+static pc_status grow_cand(pc_context *ctx, State &S, long long cap) {
+  const size_t per = 2 * sizeof(int) + sizeof(double);
+  HIPCHK(grow(ctx->cand, (size_t)cap * per + 1024));
+  const long long cc = (long long)((ctx->cand.bytes - 1024) / per);
+  S.cand_cap = cc;
+  S.cd_lb = (double *)ctx->cand.p;
+  S.cd_t = (int *)(S.cd_lb + cc);
+  S.cd_c = S.cd_t + cc;
+  return PC_OK;
+}
+
 pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int points_on_device,
                  int32_t linkage, const pc_options *opt, pc_merge *out, int out_on_device, void *stream,
                  pc_stats *stats) {
@@ -300,12 +313,12 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   S.timing = (opt && opt->timing) ? 1 : 0;
   S.tev = ctx->tev;
   S.xin = nullptr;  // set once the device copy of the points is known
-  double kms[3] = {0, 0, 0};
-  long long klaunch[3] = {0, 0, 0};
+  double kms[4] = {0, 0, 0, 0};
+  long long klaunch[4] = {0, 0, 0, 0};
   // after a synchronisation: add the timed kernels of the last round
   auto take_times = [&]() {
     if (!S.timing) return;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 4; ++k)
       if (S.tlaunched[k]) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, S.tev[2 * k], S.tev[2 * k + 1]) == hipSuccess) kms[k] += ms;
@@ -332,6 +345,12 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     if (st != PC_OK) return st;
     st = grow_fidx(ctx, S, linkage == kComplete ? std::max<long long>(1 << 22, 4 * n) : 1);
     if (st != PC_OK) return st;
+    st = grow_cand(ctx, S, std::max<long long>(1 << 22, 4 * n));
+    if (st != PC_OK) return st;
+    // test hooks: shrink the candidate record / pair list to exercise their
+    // overflow paths (capacities only ever limit, never extend, the buffers)
+    if (const char *e = getenv("PC_TEST_CAND_CAP")) S.cand_cap = std::min<long long>(S.cand_cap, atoll(e));
+    if (const char *e = getenv("PC_TEST_PAIR_CAP")) S.pair_cap = std::min<long long>(S.pair_cap, atoll(e));
   }
 
   HIPCHK(hipMemsetAsync(S.cnt, 0, sizeof(Counters), s));
@@ -360,14 +379,29 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     if (need_pairs) {
       HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      if (h.cand_overflow) {
+        // this round: emit by re-walking the rings; later rounds: a larger record
+        launch_emit_fallback(S, nact, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        pc_status st = grow_cand(ctx, S, (long long)h.n_cand + h.n_cand / 2 + 1024);
+        if (st != PC_OK) return st;
+      }
       if (h.n_pairs > S.pair_cap) {
-        S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = 0;  // the round is redone
+        S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;  // the round is redone
         pc_status st = grow_pairs(ctx, S, (long long)h.n_pairs + h.n_pairs / 2 + 1024);
         if (st != PC_OK) return st;
         launch_round(S, (int)rounds, nact, s, need_pairs);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (h.cand_overflow) {
+          launch_emit_fallback(S, nact, s);
+          HIPCHK(hipGetLastError());
+          HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+        }
         if (h.n_pairs > S.pair_cap) return fail(PC_ERR_DEVICE, "pair list overflow");
       }
       const int np = h.n_pairs;
@@ -436,10 +470,11 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     stats->ms_rounds = t12;
     stats->ms_finalize = t23;
     stats->ms_total = t03;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
       stats->kernel_ms[k] = kms[k];
       stats->kernel_launches[k] = klaunch[k];
     }
+    for (int k = 0; k < 4; ++k) stats->candidate_visits[k] = h.visits[k];
   }
   g_err.clear();
   return PC_OK;

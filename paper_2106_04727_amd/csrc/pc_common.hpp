@@ -68,12 +68,15 @@ struct Counters {
   int pair_overflow;
   int n_min;
   int nonfinite;
+  int n_cand;
+  int cand_overflow;
   unsigned long long bb_lo[2];
   unsigned long long bb_hi[2];
   long long cluster_evals;
   long long point_pairs;
   long long n_tiles;
   long long n_chunks;
+  long long visits[4];  // per timed search kernel
 };
 
 // All device arrays of one clustering call. Slots are storage indices of
@@ -141,13 +144,17 @@ struct State {
   int *pr_kR, *pr_kS;   // complete: points of each side kept by the filter
   int *fidx;            // complete: kept point positions, 256-aligned region per pair
   long long fidx_cap;
+  // large candidates recorded by the bound pass (terminal index, slot, lower bound)
+  int *cd_t, *cd_c;
+  double *cd_lb;
+  long long cand_cap;
   double *tile_v;
   long long pair_cap, tile_cap;
   int cell_cap;
   // optional kernel timing: event pairs around ring search, full scan, tiles
   int timing;
-  hipEvent_t *tev;      // 6 events (start/end per kernel), owned by the context
-  int tlaunched[3];     // kernels launched since the last read (host side)
+  hipEvent_t *tev;      // 8 events (start/end per kernel), owned by the context
+  int tlaunched[4];     // kernels launched since the last read (host side)
 };
 
 // ------------------------------------------------------ launch wrappers ----
@@ -162,9 +169,11 @@ void radix_sort_pairs(unsigned long long *&k0, unsigned long long *&k1, unsigned
 int radix_hist_len(int n);
 
 // round kernels (pc_round.hip)
+hipError_t set_direction_table();  // once per device, before the first call
 void launch_check_finite(const float *x, long long count, Counters *cnt, hipStream_t s);
 void launch_init(State &S, const float *x, hipStream_t s);
 void launch_round(State &S, int round, int nact_host, hipStream_t s, bool &need_pairs);
+void launch_emit_fallback(State &S, int nact_host, hipStream_t s);
 void launch_pairs(State &S, int round, int npairs_host, long long ntiles_host, hipStream_t s);
 void launch_pairs_prefix(State &S, int npairs_host, hipStream_t s);
 void launch_round_tail(State &S, int round, int nact_host, int merges_before, hipStream_t s);

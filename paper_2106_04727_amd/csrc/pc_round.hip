@@ -103,6 +103,8 @@ __device__ __forceinline__ unsigned long long make_key(int cid, int slot) {
 // ------------------------------------------------------------------ init --
 __global__ void k_reset_round(Counters *c) {
   c->n_ovf = 0;
+  c->n_cand = 0;
+  c->cand_overflow = 0;
   c->n_pairs = 0;
   c->pair_overflow = 0;
   c->n_min = 0x7fffffff;
@@ -427,19 +429,24 @@ __device__ __forceinline__ void pair_bounds(const double *ct, const float *lt, c
 // The half-planes u_k . x <= u_k . s_k enclose the cluster; the farthest
 // distance from a point to the cluster is at most its farthest distance to
 // that K-gon's vertices (upper bound).
-__device__ __forceinline__ void sup_dir(int k, double &c, double &s) { sincospi(2.0 * k / kSupDirs, &s, &c); }
+__constant__ double c_dir[2][kSupDirs];  // cos, sin of 2 pi k / kSupDirs (set by the host)
 
+__device__ __forceinline__ void sup_dir(int k, double &c, double &s) {
+  c = c_dir[0][k];
+  s = c_dir[1][k];
+}
+
+// farthest pair among exactly opposite support points: for the farthest pair
+// (a*, b*) and the direction u_k nearest to a* - b*, |s_k(A) - s_{k+K/2}(B)|
+// >= u_k . (a* - b*) >= cos(pi/K) |a* - b*|
 __device__ double sup_pair_lb(const float *x, const int *sa, const int *sb) {
   double m = 0.0;
   for (int k = 0; k < kSupDirs; ++k) {
     const float *pa = x + (size_t)sa[k] * 2;
-    for (int j = -2; j <= 2; ++j) {
-      const int kk = (k + kSupDirs / 2 + j + kSupDirs) % kSupDirs;
-      const float *pb = x + (size_t)sb[kk] * 2;
-      const double u = (double)pa[0] - (double)pb[0], v = (double)pa[1] - (double)pb[1];
-      const double q = u * u + v * v;
-      m = q > m ? q : m;
-    }
+    const float *pb = x + (size_t)sb[(k + kSupDirs / 2) % kSupDirs] * 2;
+    const double u = (double)pa[0] - (double)pb[0], v = (double)pa[1] - (double)pb[1];
+    const double q = u * u + v * v;
+    m = q > m ? q : m;
   }
   return m;
 }
@@ -479,7 +486,8 @@ __device__ __forceinline__ void comp_ub_refine(const State &S, int t, int c, con
   ub = us < ub ? us : ub;
 }
 
-__device__ __forceinline__ void comp_lb_refine(const State &S, int t, int c, int d, double &lb) {
+__device__ __forceinline__ void comp_lb_refine(const State &S, int t, int c, int d, double &lb,
+                                               double stop = INFINITY) {
   if (d <= kExtMaxDim) {
     const int *et = S.ext + (size_t)t * 2 * d, *ec = S.ext + (size_t)c * 2 * d;
     double m = 0.0;
@@ -497,7 +505,7 @@ __device__ __forceinline__ void comp_lb_refine(const State &S, int t, int c, int
     }
     lb = m > lb ? m : lb;
   }
-  if (d == 2) {
+  if (d == 2 && lb <= stop) {
     const double m = sup_pair_lb(S.xin, S.sup + (size_t)t * kSupDirs, S.sup + (size_t)c * kSupDirs);
     lb = m > lb ? m : lb;
   }
@@ -538,7 +546,7 @@ template <int LINK, int MAXD, int PASS>
 __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
   const int nterm = S.cnt->n_term;
   const int ti = blockIdx.x * blockDim.x + threadIdx.x;
-  long long evals = 0, ppairs = 0;
+  long long evals = 0, ppairs = 0, visits = 0;
   if (ti < nterm) {
     const GridParams g = *S.grid;
     const int d = S.d;
@@ -621,6 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
           for (int yy = 0; yy < ny; ++yy) {
             const int row = y + yy * ystep;
             const int a = S.cell_start[row * g.G[0] + x0], b = S.cell_start[row * g.G[0] + x1 + 1];
+            visits += b - a;
             for (int it = a; it < b; ++it) {
               const int4 mt = S.item_meta[it];
               const int s = mt.x;
@@ -651,11 +660,22 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                 const double cur = PASS == 0 ? fmin(bound, bestv) : bound;
                 if (lb > cur * kSlack) continue;
                 const long long cost = (long long)n_t * (long long)mt.y;
+                if (PASS == 0 && cost > kInlinePairs) {
+                  // remember it: the final bound decides later whether it is evaluated
+                  const int ci = atomicAdd(&S.cnt->n_cand, 1);
+                  if (ci < S.cand_cap) {
+                    S.cd_t[ci] = ti;
+                    S.cd_c[ci] = s;
+                    S.cd_lb[ci] = lb;
+                  } else {
+                    S.cnt->cand_overflow = 1;
+                  }
+                }
                 if (LINK == kComplete && cost > kInlinePairs) {
                   if (PASS == 0) {
                     comp_ub_refine(S, t, s, ct, cv, d, ub);
                   } else {
-                    comp_lb_refine(S, t, s, d, lb);
+                    comp_lb_refine(S, t, s, d, lb, cur * kSlack);
                     if (lb > cur * kSlack) continue;
                   }
                 }
@@ -679,6 +699,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                   if (p < S.pair_cap) {
                     S.pr_t[p] = ti;
                     S.pr_c[p] = s;
+                    S.pr_v[p] = -1.0;
                   } else {
                     S.cnt->pair_overflow = 1;
                   }
@@ -715,6 +736,38 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
   }
   count_add(&S.cnt->cluster_evals, evals);
   count_add(&S.cnt->point_pairs, ppairs);
+  count_add(&S.cnt->visits[PASS == 0 ? 0 : 3], visits);
+}
+
+// Recorded large candidates: keep those whose lower bound does not exceed
+// their terminal's final bound (refined bounds for complete), emit them as
+// pairs. Does nothing if the record overflowed (the host then re-walks the
+// rings instead).
+template <int LINK>
+__global__ void k_cand_emit(State S, const int *t_ovf) {
+  if (S.cnt->cand_overflow) return;
+  const int nc = S.cnt->n_cand;
+  const int d = S.d;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+    const int ti = S.cd_t[i];
+    if (t_ovf[ti]) continue;
+    const double beta = S.t_beta[ti] * kSlack;
+    double lb = S.cd_lb[i];
+    if (lb > beta * kSlack) continue;
+    const int c = S.cd_c[i];
+    if (LINK == kComplete) {
+      comp_lb_refine(S, S.term[ti], c, d, lb, beta * kSlack);
+      if (lb > beta * kSlack) continue;
+    }
+    const int p = atomicAdd(&S.cnt->n_pairs, 1);
+    if (p < S.pair_cap) {
+      S.pr_t[p] = ti;
+      S.pr_c[p] = c;
+      S.pr_v[p] = LINK == kComplete ? lb : -1.0;  // complete: the refined lower bound, reused
+    } else {
+      S.cnt->pair_overflow = 1;
+    }
+  }
 }
 
 // ------------------------------------------------ block ring search ------
@@ -744,7 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
   const GridParams g = *S.grid;
   const int d = S.d;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  long long evals = 0, ppairs = 0;
+  long long evals = 0, ppairs = 0, visits = 0;
   for (int qi = blockIdx.x; qi < count; qi += gridDim.x) {
     const int ti = S.ovf[qi];
     const int t = S.term[ti];
@@ -810,6 +863,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
           const double Dc = fmax(0.0, sqrt(dx * dx + dy * dy) * (1.0 - 1e-9) - g.eps);
           const double mycur = pass == 0 ? fmin(cur, fmin(bound, bestv)) : cur;
           if (cell_key_lb<LINK>(Dc, nt, S.cell_nmin[cell]) > mycur) continue;
+          visits += b - a;
           for (int it = a; it < b; ++it) {
             const int4 mt = S.item_meta[it];
             const int sl = mt.x;
@@ -842,7 +896,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
                 if (pass == 0) {
                   comp_ub_refine(S, t, sl, ct, cv, d, ub);
                 } else {
-                  comp_lb_refine(S, t, sl, d, lb);
+                  comp_lb_refine(S, t, sl, d, lb, c2 * kSlack);
                   if (lb > c2 * kSlack) continue;
                 }
               }
@@ -865,6 +919,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
                 if (pp < S.pair_cap) {
                   S.pr_t[pp] = ti;
                   S.pr_c[pp] = sl;
+                  S.pr_v[pp] = -1.0;
                 } else {
                   S.cnt->pair_overflow = 1;
                 }
@@ -953,6 +1008,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
   }
   count_add(&S.cnt->cluster_evals, evals);
   count_add(&S.cnt->point_pairs, ppairs);
+  count_add(&S.cnt->visits[1], visits);
 }
 
 // ---------------------------------------------------- full scan kernel ----
@@ -970,7 +1026,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
   __shared__ double red_v[kBlock / kWave];
   __shared__ unsigned long long red_k[kBlock / kWave];
   __shared__ double red_b[kBlock / kWave];
-  long long evals = 0, ppairs = 0;
+  long long evals = 0, ppairs = 0, visits = 0;
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
     const int ti = list ? list[q] : q;
     const int t = S.term[ti];
@@ -991,6 +1047,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
     unsigned long long bestk = kNoKey;
     for (int i = threadIdx.x; i < nact; i += blockDim.x) {
       const int s = S.act[i];
+      ++visits;
       if (s == t) continue;
       const unsigned long long key = make_key(S.cid[s], s);
       const int n_c = S.csize[s];
@@ -1076,7 +1133,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
                                d, lb, ub);
           if (lb > beta * kSlack) continue;
           if (LINK == kComplete) {
-            comp_lb_refine(S, t, s, d, lb);
+            comp_lb_refine(S, t, s, d, lb, beta * kSlack);
             if (lb > beta * kSlack) continue;
           }
         }
@@ -1084,6 +1141,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
         if (p < S.pair_cap) {
           S.pr_t[p] = ti;
           S.pr_c[p] = s;
+          S.pr_v[p] = -1.0;
         } else {
           S.cnt->pair_overflow = 1;
         }
@@ -1093,6 +1151,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
   }
   count_add(&S.cnt->cluster_evals, evals);
   count_add(&S.cnt->point_pairs, ppairs);
+  count_add(&S.cnt->visits[1], visits);
 }
 
 // ---------------------------------------------------------- pair tiles ----
@@ -1214,12 +1273,14 @@ __global__ void k_pair_prep_comp(State S, long long *nch) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
     int r, q;
     pair_slots(S, p, r, q);
-    const double *cr = S.wcen + (size_t)r * d, *cq = S.wcen + (size_t)q * d;
-    double lb, ub;
-    pair_bounds<kComplete, 0>(cr, S.lo + (size_t)r * d, S.hi + (size_t)r * d, cq, S.lo + (size_t)q * d,
-                              S.hi + (size_t)q * d, d, lb, ub);
-    comp_refine(S, r, q, cr, cq, d, lb, ub);
-    S.pr_v[p] = lb;
+    if (!(S.pr_v[p] >= 0.0)) {
+      const double *cr = S.wcen + (size_t)r * d, *cq = S.wcen + (size_t)q * d;
+      double lb, ub;
+      pair_bounds<kComplete, 0>(cr, S.lo + (size_t)r * d, S.hi + (size_t)r * d, cq, S.lo + (size_t)q * d,
+                                S.hi + (size_t)q * d, d, lb, ub);
+      comp_lb_refine(S, r, q, d, lb);
+      S.pr_v[p] = lb;
+    }
     S.pr_kR[p] = 0;
     S.pr_kS[p] = 0;
     nch[p] = (S.csize[r] + S.csize[q] + kChunk - 1) / kChunk;
@@ -1534,16 +1595,6 @@ __global__ void k_merge(State S, int base) {
       }
       const double ra = sqrt(da) + S.crad[a], rb = sqrt(db) + S.crad[b];
       S.crad[a] = (ra > rb ? ra : rb) * (1.0 + 1e-12);
-      if (d == 2)
-        for (int k = 0; k < kSupDirs; ++k) {
-          int *sa = S.sup + (size_t)a * kSupDirs + k;
-          const int sb = S.sup[(size_t)b * kSupDirs + k];
-          double c, sn;
-          sup_dir(k, c, sn);
-          const float *pa = S.xin + (size_t)(*sa) * 2, *pb = S.xin + (size_t)sb * 2;
-          const double va = c * (double)pa[0] + sn * (double)pa[1], vb = c * (double)pb[0] + sn * (double)pb[1];
-          if (vb > va || (vb == va && sb < *sa)) *sa = sb;
-        }
       if (d <= kExtMaxDim)
         for (int k = 0; k < d; ++k) {
           int *ea = S.ext + (size_t)a * 2 * d, *eb = S.ext + (size_t)b * 2 * d;
@@ -1573,6 +1624,23 @@ __global__ void k_merge(State S, int base) {
     S.alive[b] = 0;
     S.succ[b] = -1;
     S.node[b] = -1;
+  }
+}
+
+// support points of merged clusters (d == 2): thread per (merge, direction)
+__global__ void k_merge_sup(State S) {
+  const long long total = (long long)S.cnt->n_merge * kSupDirs;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int m = (int)(i / kSupDirs), k = (int)(i % kSupDirs);
+    const int a = S.m_a[m], b = S.m_b[m];
+    int *sa = S.sup + (size_t)a * kSupDirs + k;
+    const int sb = S.sup[(size_t)b * kSupDirs + k];
+    double c, sn;
+    sup_dir(k, c, sn);
+    const float *pa = S.xin + (size_t)(*sa) * 2, *pb = S.xin + (size_t)sb * 2;
+    const double va = c * (double)pa[0] + sn * (double)pa[1], vb = c * (double)pb[0] + sn * (double)pb[1];
+    if (vb > va || (vb == va && sb < *sa)) *sa = sb;
   }
 }
 
@@ -1701,14 +1769,26 @@ void launch_emit(State &S, int nact, hipStream_t s, int *t_ovf) {
   // pass 1 of the ring search; the full-scan kernel already emitted its pairs
   if (S.d <= kGridMaxDim && S.prune) {
     const int tb = nblk(nact, 1 << 20);
+    tmark(S, 3, false, s);
     if (S.d <= 2) k_nn_grid<LINK, 2, 1><<<tb, kBlock, 0, s>>>(S, t_ovf);
     else if (S.d <= 4) k_nn_grid<LINK, 4, 1><<<tb, kBlock, 0, s>>>(S, t_ovf);
     else if (S.d <= 8) k_nn_grid<LINK, 8, 1><<<tb, kBlock, 0, s>>>(S, t_ovf);
     else k_nn_grid<LINK, 16, 1><<<tb, kBlock, 0, s>>>(S, t_ovf);
+    tmark(S, 3, true, s);
   }
 }
 
 }  // namespace
+
+hipError_t set_direction_table() {
+  double t[2][kSupDirs];
+  for (int k = 0; k < kSupDirs; ++k) {
+    const double a = 2.0 * M_PI * (double)k / (double)kSupDirs;
+    t[0][k] = cos(a);
+    t[1][k] = sin(a);
+  }
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_dir), t, sizeof(t));
+}
 
 void launch_check_finite(const float *x, long long count, Counters *cnt, hipStream_t s) {
   k_check_finite<<<nblk(count, 2048), kBlock, 0, s>>>(x, count, cnt);
@@ -1745,9 +1825,32 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
   need_pairs = false;
   switch (S.linkage) {
   case kWard: launch_search<kWard>(S, nact, s, t_ovf); break;
-  case kComplete: launch_search<kComplete>(S, nact, s, t_ovf); launch_emit<kComplete>(S, nact, s, t_ovf); need_pairs = true; break;
-  default: launch_search<kAverage>(S, nact, s, t_ovf); launch_emit<kAverage>(S, nact, s, t_ovf); need_pairs = true; break;
+  case kComplete:
+    launch_search<kComplete>(S, nact, s, t_ovf);
+    if (S.d <= kGridMaxDim && S.prune) {
+      tmark(S, 3, false, s);
+      k_cand_emit<kComplete><<<2048, kBlock, 0, s>>>(S, t_ovf);
+      tmark(S, 3, true, s);
+    }
+    need_pairs = true;
+    break;
+  default:
+    launch_search<kAverage>(S, nact, s, t_ovf);
+    if (S.d <= kGridMaxDim && S.prune) {
+      tmark(S, 3, false, s);
+      k_cand_emit<kAverage><<<2048, kBlock, 0, s>>>(S, t_ovf);
+      tmark(S, 3, true, s);
+    }
+    need_pairs = true;
+    break;
   }
+}
+
+// The record of large candidates overflowed: emit by re-walking the rings.
+void launch_emit_fallback(State &S, int nact, hipStream_t s) {
+  int *t_ovf = S.cell_rank;
+  if (S.linkage == kComplete) launch_emit<kComplete>(S, nact, s, t_ovf);
+  else if (S.linkage == kAverage) launch_emit<kAverage>(S, nact, s, t_ovf);
 }
 
 void launch_pairs_prefix(State &S, int npairs, hipStream_t s) {
@@ -1799,6 +1902,8 @@ void launch_round_tail(State &S, int round, int nact, int merges_before, hipStre
   scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_term, &S.cnt->n_merge, S.part, s);
   k_rnn_scatter<<<gb, kBlock, 0, s>>>(S);
   k_merge<<<nblk(nact / 2 + 1, 2048), kBlock, 0, s>>>(S, merges_before);
+  if (S.linkage == kComplete && S.d == 2)
+    k_merge_sup<<<nblk((long long)(nact / 2 + 1) * kSupDirs, 8192), kBlock, 0, s>>>(S);
   k_alive_flags<<<gb, kBlock, 0, s>>>(S);
   int *total = S.scan + S.n;  // one spare int past the scan array
   scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, total, S.part, s);

@@ -53,15 +53,16 @@ class pc_stats(ctypes.Structure):
                 ("cluster_evals", ctypes.c_int64), ("point_pair_evals", ctypes.c_int64),
                 ("overflow_queries", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("ms_init", ctypes.c_double), ("ms_rounds", ctypes.c_double),
-                ("ms_finalize", ctypes.c_double), ("kernel_ms", ctypes.c_double * 3),
-                ("kernel_launches", ctypes.c_int64 * 3)]
+                ("ms_finalize", ctypes.c_double), ("kernel_ms", ctypes.c_double * 4),
+                ("kernel_launches", ctypes.c_int64 * 4), ("candidate_visits", ctypes.c_int64 * 4)]
 
-    KERNELS = ("ring_search", "full_scan", "pair_tiles")
+    KERNELS = ("ring_search", "block_search", "pair_tiles", "ring_emit")
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_
-             if k not in ("struct_size", "reserved", "kernel_ms", "kernel_launches")}
-        d["kernels"] = {k: {"ms": self.kernel_ms[i], "launches": self.kernel_launches[i]}
+             if k not in ("struct_size", "reserved", "kernel_ms", "kernel_launches", "candidate_visits")}
+        d["kernels"] = {k: {"ms": self.kernel_ms[i], "launches": self.kernel_launches[i],
+                            "visits": self.candidate_visits[i]}
                         for i, k in enumerate(self.KERNELS)}
         return d
 

@@ -150,3 +150,18 @@ def test_nonfinite_rejected(pc):
     x[5, 1] = np.inf
     with pytest.raises(PCError):
         pc.hac(x, "complete")
+
+
+@pytest.mark.parametrize("link", ["complete", "average"])
+def test_overflow_paths(pc, link, monkeypatch):
+    """Tiny candidate-record and pair-list capacities force the ring re-walk
+    fallback and the pair-list regrow; results must not change."""
+    x = synth.blobs(4000, 2, 12, 0.03, 31)
+    Z0 = pc.hac(x, link)
+    monkeypatch.setenv("PC_TEST_CAND_CAP", "16")
+    Z1 = pc.hac(x, link)
+    monkeypatch.setenv("PC_TEST_PAIR_CAP", "8")
+    Z2 = pc.hac(x, link)
+    assert np.array_equal(Z0, Z1) and np.array_equal(Z0, Z2)
+    Zo, _ = oracle.nnchain(x, link, threads=8)
+    assert _trees.same_tree(Z0, Zo, 4000, rtol=RTOL[link])
