@@ -57,6 +57,9 @@ def _load():
             ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
             i64p, i64p, f64p, i64p, f64p,
         ]
+        lib.oracle_tree_sums.restype = ctypes.c_int
+        lib.oracle_tree_sums.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_linkage.restype = ctypes.c_double
         lib.oracle_linkage.argtypes = [
             ctypes.c_void_p, ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int64, i64p, ctypes.c_int64,
@@ -110,6 +113,33 @@ def linkage_dist(x: np.ndarray, linkage, A, B) -> float:
     return float(_load().oracle_linkage(
         x.ctypes.data, x.shape[1], _code(linkage), _ptr(A, ctypes.c_int64), A.size,
         _ptr(B, ctypes.c_int64), B.size))
+
+
+def tree_sums(x: np.ndarray, Z: np.ndarray):
+    """FP64 coordinate sums and sizes of all 2n-1 nodes of dendrogram Z."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    n, d = x.shape
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    sums = np.zeros((2 * n - 1, d), np.float64)
+    sizes = np.zeros(2 * n - 1, np.int64)
+    rc = _load().oracle_tree_sums(x.ctypes.data, n, d, Z.ctypes.data, sums.ctypes.data, sizes.ctypes.data)
+    if rc != 0:
+        raise ValueError("rows are not a valid creation order")
+    return sums, sizes
+
+
+def node_members(Z: np.ndarray, n: int, node: int) -> np.ndarray:
+    """Point indices under one node (iterative walk)."""
+    out, stack = [], [int(node)]
+    while stack:
+        v = stack.pop()
+        if v < n:
+            out.append(v)
+        else:
+            r = v - n
+            stack.append(int(Z[r, 0]))
+            stack.append(int(Z[r, 1]))
+    return np.array(sorted(out), np.int64)
 
 
 def members(Z: np.ndarray, n: int):

@@ -293,3 +293,27 @@ double oracle_linkage(const float *x, int d, int linkage, const int64_t *A, int6
     }
     return NAN;
 }
+
+/*
+ * Coordinate sums and sizes of every node of a dendrogram given as rows
+ * (a, b, height, size) in a valid creation order (children before parents,
+ * leaves 0..n-1, row r creates node n+r). Used by the tests to recompute
+ * Ward distances between arbitrary live clusters at full scale.
+ *   sums  (2n-1) x d doubles, sizes (2n-1)
+ * Returns 0, or -1 if a row references a node not yet created.
+ */
+int oracle_tree_sums(const float *x, int64_t n, int d, const double *rows, double *sums, int64_t *sizes)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        sizes[i] = 1;
+        for (int k = 0; k < d; ++k) sums[(size_t)i * d + k] = (double)x[(size_t)i * d + k];
+    }
+    for (int64_t r = 0; r + 1 < n; ++r) {
+        int64_t a = (int64_t)rows[4 * r], b = (int64_t)rows[4 * r + 1], c = n + r;
+        if (a < 0 || b < 0 || a >= c || b >= c) return -1;
+        sizes[c] = sizes[a] + sizes[b];
+        for (int k = 0; k < d; ++k)
+            sums[(size_t)c * d + k] = sums[(size_t)a * d + k] + sums[(size_t)b * d + k];
+    }
+    return 0;
+}
