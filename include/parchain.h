@@ -72,6 +72,11 @@ typedef struct {
                           (same result, for ablations and tests) */
     int32_t timing;    /* 1: time the search and tile kernels with HIP events
                           on the call's stream (fills the kernel_* stats) */
+    int32_t cache_slots; /* cluster-pair distance cache (Alg. 4, Sec. 5):
+                          capacity ~ cache_slots * n entries; -1 = default
+                          (64 for average, 0 = off for complete and Ward,
+                          the paper's settings) */
+    int32_t reserved;
 } pc_options;
 
 /* Counters of one pc_hac call; struct_size must be sizeof(pc_stats). */
@@ -94,6 +99,9 @@ typedef struct {
                                  [3] ring search (pair emission pass) */
     int64_t kernel_launches[4];
     int64_t candidate_visits[4]; /* candidate clusters examined, per kernel above */
+    int64_t cache_hits;       /* pair distances reused from the cache */
+    int64_t cache_inserts;    /* cache slots taken (claims and stores) */
+    int64_t cache_fail;       /* stores dropped because the probe window was full */
 } pc_stats;
 
 typedef struct pc_context pc_context;

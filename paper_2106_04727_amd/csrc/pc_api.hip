@@ -53,6 +53,7 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   S.cid = c.take<int>(n);
   S.csize = c.take<int>(n);
   S.node = c.take<int>(n);
+  S.node2slot = c.take<int>(2 * n);
   S.succ = c.take<int>(n);
   S.succ_node = c.take<int>(n);
   S.predd = c.take<unsigned>(n);
@@ -142,7 +143,7 @@ hipError_t grow(Buf &b, size_t bytes) {
 
 struct pc_context {
   int device = 0;
-  Buf ws, pairs, tiles, part, fidx, cand;
+  Buf ws, pairs, tiles, part, fidx, cand, cache[2];
   Counters *hcnt = nullptr;  // pinned host mirror of the device counters
   hipEvent_t ev[4] = {};
   hipEvent_t tev[8] = {};
@@ -190,6 +191,8 @@ void pc_context_destroy(pc_context *c) {
   if (c->part.p) hipFree(c->part.p);
   if (c->fidx.p) hipFree(c->fidx.p);
   if (c->cand.p) hipFree(c->cand.p);
+  for (int i = 0; i < 2; ++i)
+    if (c->cache[i].p) hipFree(c->cache[i].p);
   if (c->hcnt) hipHostFree(c->hcnt);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) hipEventDestroy(c->ev[i]);
@@ -205,8 +208,15 @@ size_t pc_hac_workspace_bytes(int64_t n, int32_t d, int32_t linkage, const pc_op
   size_t bytes = layout(S, nullptr, n, d, linkage, true);
   if (linkage != kWard) {
     const size_t pc = (size_t)std::max<int64_t>(1 << 20, 2 * n);
-    bytes += pc * (3 * sizeof(long long) + 4 * sizeof(int)) + 1024;
+    bytes += pc * (3 * sizeof(long long) + 6 * sizeof(int)) + 1024;
     if (linkage == kAverage) bytes += ((size_t)1 << 22) * sizeof(double);
+    int cs = opt ? opt->cache_slots : -1;
+    if (cs < 0) cs = linkage == kAverage ? 64 : 0;
+    if (cs > 0) {
+      size_t cap = (size_t)1 << 16;
+      while (cap < (size_t)n * (size_t)cs && cap < ((size_t)1 << 31)) cap <<= 1;
+      bytes += 2 * cap * 2 * sizeof(unsigned long long);
+    }
   }
   return bytes;
 }
@@ -221,8 +231,9 @@ static pc_status grow_part(pc_context *ctx, State &S, long long longest_scan) {
 }
 
 static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
-  // per pair: tile prefix (i64), chunk prefix (i64), value (f64), t, c, kR, kS (i32)
-  const size_t per = 3 * sizeof(long long) + 4 * sizeof(int);
+  // per pair: tile prefix (i64), chunk prefix (i64), value (f64), t, c, kR, kS,
+  // pending t, pending c (i32)
+  const size_t per = 3 * sizeof(long long) + 6 * sizeof(int);
   HIPCHK(grow(ctx->pairs, (size_t)cap * per + 1024));
   char *b = (char *)ctx->pairs.p;
   const long long pc = (long long)((ctx->pairs.bytes - 1024) / per);
@@ -234,6 +245,8 @@ static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
   S.pr_c = S.pr_t + pc;
   S.pr_kR = S.pr_c + pc;
   S.pr_kS = S.pr_kR + pc;
+  S.pd_t = S.pr_kS + pc;
+  S.pd_c = S.pd_t + pc;
   return grow_part(ctx, S, std::max<long long>(S.pair_cap, 2LL * S.n + 64));
 }
 
@@ -275,6 +288,9 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   if (opt && opt->struct_size != sizeof(pc_options)) return fail(PC_ERR_INVALID_ARG, "pc_options.struct_size");
   if (stats && stats->struct_size != sizeof(pc_stats)) return fail(PC_ERR_INVALID_ARG, "pc_stats.struct_size");
   const int prune = opt ? (opt->prune != 0) : 1;
+  int cache_slots = opt ? opt->cache_slots : -1;
+  if (cache_slots < 0) cache_slots = linkage == kAverage ? 64 : 0;
+  if (linkage == kWard) cache_slots = 0;  // Ward distances cost less than a probe
   if (opt && opt->precision != PC_PREC_EXACT) return fail(PC_ERR_UNSUPPORTED, "precision mode not available");
   if (!points_on_device) {
     for (int64_t i = 0; i < n * (int64_t)d; ++i)
@@ -353,6 +369,25 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     if (const char *e = getenv("PC_TEST_PAIR_CAP")) S.pair_cap = std::min<long long>(S.pair_cap, atoll(e));
   }
 
+  // cluster-pair cache: two tables (the second receives the live entries at a rebuild)
+  int cache_cur = 0;
+  long long cache_base = 0;  // inserts counted when the current table was filled
+  if (cache_slots > 0) {
+    unsigned long long cap = 1ull << 16;
+    while (cap < (unsigned long long)n * (unsigned long long)cache_slots && cap < (1ull << 31)) cap <<= 1;
+    // test hook: a small table exercises rebuilds and full probe windows
+    if (const char *e = getenv("PC_TEST_CACHE_CAP")) {
+      unsigned long long want = (unsigned long long)atoll(e), c2 = 64;
+      while (c2 < want) c2 <<= 1;
+      if (c2 < cap) cap = c2;
+    }
+    for (int i = 0; i < 2; ++i) HIPCHK(grow(ctx->cache[i], (size_t)cap * 2 * sizeof(unsigned long long)));
+    S.cache_mask = cap - 1;
+    S.ck = (unsigned long long *)ctx->cache[0].p;
+    S.cv = S.ck + cap;
+    launch_cache_clear(S, S.ck, S.cv, S.cache_mask, s);
+    HIPCHK(hipGetLastError());
+  }
   HIPCHK(hipMemsetAsync(S.cnt, 0, sizeof(Counters), s));
   HIPCHK(hipEventRecord(ctx->ev[0], s));
   if (points_on_device) {
@@ -388,9 +423,11 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
         pc_status st = grow_cand(ctx, S, (long long)h.n_cand + h.n_cand / 2 + 1024);
         if (st != PC_OK) return st;
       }
-      if (h.n_pairs > S.pair_cap) {
+      if (h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap) {
         S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;  // the round is redone
-        pc_status st = grow_pairs(ctx, S, (long long)h.n_pairs + h.n_pairs / 2 + 1024);
+        launch_cache_unclaim(S, s);
+        const long long want = std::max<long long>(h.n_pairs, h.n_pend);
+        pc_status st = grow_pairs(ctx, S, want + want / 2 + 1024);
         if (st != PC_OK) return st;
         launch_round(S, (int)rounds, nact, s, need_pairs);
         HIPCHK(hipGetLastError());
@@ -402,7 +439,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
           HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
           HIPCHK(hipStreamSynchronize(s));
         }
-        if (h.n_pairs > S.pair_cap) return fail(PC_ERR_DEVICE, "pair list overflow");
+        if (h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap) return fail(PC_ERR_DEVICE, "pair list overflow");
       }
       const int np = h.n_pairs;
       launch_pairs_prefix(S, np, s);
@@ -438,6 +475,19 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     HIPCHK(hipStreamSynchronize(s));
     if (h.nonfinite == 2) return fail(PC_ERR_DEVICE, "a terminal found no neighbour");
     if (h.nonfinite == 3) return fail(PC_ERR_DEVICE, "internal index check failed");
+    if (h.nonfinite == 4) return fail(PC_ERR_DEVICE, "a claimed cache entry was never filled");
+    if (S.cache_mask && h.cache_inserts - cache_base > (long long)(S.cache_mask + 1) / 2) {
+      // rebuild: keep only entries whose two clusters are still alive
+      const int nxt = 1 - cache_cur;
+      unsigned long long *ok = S.ck, *ov = S.cv;
+      S.ck = (unsigned long long *)ctx->cache[nxt].p;
+      S.cv = S.ck + (S.cache_mask + 1);
+      launch_cache_clear(S, S.ck, S.cv, S.cache_mask, s);
+      launch_cache_rebuild(S, ok, ov, S.cache_mask, s);
+      HIPCHK(hipGetLastError());
+      cache_base = h.cache_inserts;
+      cache_cur = nxt;
+    }
     take_times();
     if (h.n_merge <= 0) return fail(PC_ERR_DEVICE, "round merged nothing");
     terms += h.n_term;
@@ -475,6 +525,9 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
       stats->kernel_launches[k] = klaunch[k];
     }
     for (int k = 0; k < 4; ++k) stats->candidate_visits[k] = h.visits[k];
+    stats->cache_hits = h.cache_hits;
+    stats->cache_inserts = h.cache_inserts;
+    stats->cache_fail = h.cache_fail;
   }
   g_err.clear();
   return PC_OK;

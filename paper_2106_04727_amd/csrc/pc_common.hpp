@@ -70,6 +70,11 @@ struct Counters {
   int nonfinite;
   int n_cand;
   int cand_overflow;
+  int n_pend;
+  int pad0;
+  long long cache_hits;
+  long long cache_inserts;
+  long long cache_fail;
   unsigned long long bb_lo[2];
   unsigned long long bb_hi[2];
   long long cluster_evals;
@@ -144,6 +149,12 @@ struct State {
   int *pr_kR, *pr_kS;   // complete: points of each side kept by the filter
   int *fidx;            // complete: kept point positions, 256-aligned region per pair
   long long fidx_cap;
+  // cluster-pair cache (Sec. 5): open addressing, key = (lower node << 32 | higher
+  // node), value = the pair's key value (bits); cache_mask + 1 slots, 0 = off
+  unsigned long long *ck, *cv;
+  unsigned long long cache_mask;
+  int *node2slot;       // node id -> slot (valid while the node is alive)
+  int *pd_t, *pd_c;     // pairs whose value another terminal is computing this round
   // large candidates recorded by the bound pass (terminal index, slot, lower bound)
   int *cd_t, *cd_c;
   double *cd_lb;
@@ -174,6 +185,11 @@ void launch_check_finite(const float *x, long long count, Counters *cnt, hipStre
 void launch_init(State &S, const float *x, hipStream_t s);
 void launch_round(State &S, int round, int nact_host, hipStream_t s, bool &need_pairs);
 void launch_emit_fallback(State &S, int nact_host, hipStream_t s);
+void launch_cache_clear(State &S, unsigned long long *keys, unsigned long long *vals,
+                        unsigned long long mask, hipStream_t s);
+void launch_cache_rebuild(State &S, const unsigned long long *okeys, const unsigned long long *ovals,
+                          unsigned long long omask, hipStream_t s);
+void launch_cache_unclaim(State &S, hipStream_t s);
 void launch_pairs(State &S, int round, int npairs_host, long long ntiles_host, hipStream_t s);
 void launch_pairs_prefix(State &S, int npairs_host, hipStream_t s);
 void launch_round_tail(State &S, int round, int nact_host, int merges_before, hipStream_t s);

@@ -105,6 +105,7 @@ __global__ void k_reset_round(Counters *c) {
   c->n_ovf = 0;
   c->n_cand = 0;
   c->cand_overflow = 0;
+  c->n_pend = 0;
   c->n_pairs = 0;
   c->pair_overflow = 0;
   c->n_min = 0x7fffffff;
@@ -171,6 +172,7 @@ __global__ void k_init_slots(State S, const float *x, const unsigned *perm) {
   S.cid[s] = p;
   S.csize[s] = 1;
   S.node[s] = p;
+  S.node2slot[p] = s;
   S.succ[s] = -1;
   S.succ_node[s] = -1;
   S.predd[s] = kInfBits;
@@ -421,6 +423,110 @@ __device__ __forceinline__ void pair_bounds(const double *ct, const float *lt, c
   }
 }
 
+// ------------------------------------------------ cluster-pair cache ----
+// Alg. 4 / Sec. 5: distances of cluster pairs are kept for reuse. Keys are
+// (lower node id, higher node id); node ids are never reused, so an entry of
+// a merged cluster can never match again (invalidation on merge) and is
+// dropped at the next rebuild. A slot's value is PENDING from the moment a
+// terminal claims the pair for evaluation until the value is stored, so a
+// pair is evaluated once per round however many terminals want it (the
+// paper's claim-before-compute entry).
+constexpr unsigned long long kCacheEmpty = ~0ull;
+constexpr unsigned long long kCachePending = 0xfff8000000000001ull;  // never a stored value
+constexpr int kCacheProbe = 32;
+
+__device__ __forceinline__ unsigned long long pair_key(int na, int nb) {
+  const unsigned lo = (unsigned)min(na, nb), hi = (unsigned)max(na, nb);
+  return ((unsigned long long)lo << 32) | hi;
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// 0: miss, 1: hit (value in v), 2: claimed this round, value not stored yet
+__device__ int cache_find(const State &S, unsigned long long key, double &v) {
+  if (!S.cache_mask) return 0;
+  const unsigned long long h = mix64(key);
+  for (int i = 0; i < kCacheProbe; ++i) {
+    const unsigned long long idx = (h + i) & S.cache_mask;
+    const unsigned long long k = __atomic_load_n(&S.ck[idx], __ATOMIC_RELAXED);
+    if (k == key) {
+      const unsigned long long b = __atomic_load_n(&S.cv[idx], __ATOMIC_RELAXED);
+      if (b == kCachePending) return 2;
+      v = pos_from_bits(b);
+      return 1;
+    }
+    if (k == kCacheEmpty) return 0;
+  }
+  return 0;
+}
+
+// 1: claimed (caller evaluates), 2: already present, 0: no free slot
+__device__ int cache_claim(const State &S, unsigned long long key) {
+  const unsigned long long h = mix64(key);
+  for (int i = 0; i < kCacheProbe; ++i) {
+    const unsigned long long idx = (h + i) & S.cache_mask;
+    const unsigned long long prev = atomicCAS(&S.ck[idx], kCacheEmpty, key);
+    if (prev == kCacheEmpty) {
+      atomicAdd((unsigned long long *)&S.cnt->cache_inserts, 1ull);
+      return 1;
+    }
+    if (prev == key) return 2;
+  }
+  return 0;
+}
+
+__device__ void cache_fill(const State &S, unsigned long long key, double v) {
+  const unsigned long long h = mix64(key);
+  for (int i = 0; i < kCacheProbe; ++i) {
+    const unsigned long long idx = (h + i) & S.cache_mask;
+    const unsigned long long prev = atomicCAS(&S.ck[idx], kCacheEmpty, key);
+    if (prev == kCacheEmpty || prev == key) {
+      if (prev == kCacheEmpty) atomicAdd((unsigned long long *)&S.cnt->cache_inserts, 1ull);
+      atomicExch(&S.cv[idx], pos_bits(v));
+      return;
+    }
+  }
+  atomicAdd((unsigned long long *)&S.cnt->cache_fail, 1ull);
+}
+
+__global__ void k_cache_clear(unsigned long long *keys, unsigned long long *vals, unsigned long long mask) {
+  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i <= mask;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    keys[i] = kCacheEmpty;
+    vals[i] = kCachePending;
+  }
+}
+
+__device__ __forceinline__ bool node_alive(const State &S, int v) {
+  const int sl = S.node2slot[v];
+  return sl >= 0 && S.node[sl] == v;
+}
+
+// Move the live, valued entries of an old table into the (cleared) current one.
+__global__ void k_cache_rebuild(State S, const unsigned long long *okeys, const unsigned long long *ovals,
+                                unsigned long long omask) {
+  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i <= omask;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    const unsigned long long k = okeys[i], b = ovals[i];
+    if (k == kCacheEmpty || b == kCachePending) continue;
+    const int a = (int)(k >> 32), c = (int)(k & 0xffffffffu);
+    if (!node_alive(S, a) || !node_alive(S, c)) continue;
+    cache_fill(S, k, pos_from_bits(b));
+  }
+}
+
+// Drop claims whose value never arrived (a round being redone).
+__global__ void k_cache_unclaim(State S) {
+  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i <= S.cache_mask;
+       i += (unsigned long long)gridDim.x * blockDim.x)
+    if (S.ck[i] != kCacheEmpty && S.cv[i] == kCachePending) S.ck[i] = kCacheEmpty;
+}
+
 // ---- d == 2 support polygons (complete linkage) --------------------------
 // For unit directions u_k = (cos, sin)(2 pi k / K) a cluster keeps a point
 // s_k maximising u_k . x. The farthest pair of two clusters is attained at
@@ -546,7 +652,7 @@ template <int LINK, int MAXD, int PASS>
 __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
   const int nterm = S.cnt->n_term;
   const int ti = blockIdx.x * blockDim.x + threadIdx.x;
-  long long evals = 0, ppairs = 0, visits = 0;
+  long long evals = 0, ppairs = 0, visits = 0, hits = 0;
   if (ti < nterm) {
     const GridParams g = *S.grid;
     const int d = S.d;
@@ -660,6 +766,17 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                 const double cur = PASS == 0 ? fmin(bound, bestv) : bound;
                 if (lb > cur * kSlack) continue;
                 const long long cost = (long long)n_t * (long long)mt.y;
+                if (PASS == 0 && cost > kInlinePairs && S.cache_mask) {
+                  double v;
+                  if (cache_find(S, pair_key(S.node[t], S.node[s]), v) == 1) {
+                    ++hits;
+                    if (better(v, key, bestv, bestk)) {
+                      bestv = v;
+                      bestk = key;
+                    }
+                    continue;
+                  }
+                }
                 if (PASS == 0 && cost > kInlinePairs) {
                   // remember it: the final bound decides later whether it is evaluated
                   const int ci = atomicAdd(&S.cnt->n_cand, 1);
@@ -695,6 +812,10 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                 } else if (PASS == 0) {
                   if (ub < bound) bound = ub;
                 } else {
+                  if (S.cache_mask) {
+                    double v;
+                    if (cache_find(S, pair_key(S.node[t], S.node[s]), v) == 1) continue;  // counted in pass 0
+                  }
                   const int p = atomicAdd(&S.cnt->n_pairs, 1);
                   if (p < S.pair_cap) {
                     S.pr_t[p] = ti;
@@ -737,6 +858,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
   count_add(&S.cnt->cluster_evals, evals);
   count_add(&S.cnt->point_pairs, ppairs);
   count_add(&S.cnt->visits[PASS == 0 ? 0 : 3], visits);
+  count_add(&S.cnt->cache_hits, hits);
 }
 
 // Recorded large candidates: keep those whose lower bound does not exceed
@@ -758,6 +880,20 @@ __global__ void k_cand_emit(State S, const int *t_ovf) {
     if (LINK == kComplete) {
       comp_lb_refine(S, S.term[ti], c, d, lb, beta * kSlack);
       if (lb > beta * kSlack) continue;
+    }
+    if (S.cache_mask) {
+      // claim the pair; if another terminal already did, wait for its value
+      const int r = cache_claim(S, pair_key(S.node[S.term[ti]], S.node[c]));
+      if (r == 2) {
+        const int q = atomicAdd(&S.cnt->n_pend, 1);
+        if (q < S.pair_cap) {
+          S.pd_t[q] = ti;
+          S.pd_c[q] = c;
+        } else {
+          S.cnt->pair_overflow = 1;
+        }
+        continue;
+      }
     }
     const int p = atomicAdd(&S.cnt->n_pairs, 1);
     if (p < S.pair_cap) {
@@ -797,7 +933,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
   const GridParams g = *S.grid;
   const int d = S.d;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  long long evals = 0, ppairs = 0, visits = 0;
+  long long evals = 0, ppairs = 0, visits = 0, hits = 0;
   for (int qi = blockIdx.x; qi < count; qi += gridDim.x) {
     const int ti = S.ovf[qi];
     const int t = S.term[ti];
@@ -892,6 +1028,17 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
               const double c2 = pass == 0 ? fmin(cur, fmin(bound, bestv)) : cur;
               if (lb > c2 * kSlack) continue;
               const long long cost = (long long)n_t * (long long)mt.y;
+              if (pass == 0 && cost > kInlinePairs && S.cache_mask) {
+                double v;
+                if (cache_find(S, pair_key(S.node[t], S.node[sl]), v) == 1) {
+                  ++hits;
+                  if (better(v, key, bestv, bestk)) {
+                    bestv = v;
+                    bestk = key;
+                  }
+                  continue;
+                }
+              }
               if (LINK == kComplete && cost > kInlinePairs) {
                 if (pass == 0) {
                   comp_ub_refine(S, t, sl, ct, cv, d, ub);
@@ -915,6 +1062,10 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
               } else if (pass == 0) {
                 if (ub < bound) bound = ub;
               } else {
+                if (S.cache_mask) {
+                  double v;
+                  if (cache_find(S, pair_key(S.node[t], S.node[sl]), v) == 1) continue;  // counted in pass 0
+                }
                 const int pp = atomicAdd(&S.cnt->n_pairs, 1);
                 if (pp < S.pair_cap) {
                   S.pr_t[pp] = ti;
@@ -1009,6 +1160,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
   count_add(&S.cnt->cluster_evals, evals);
   count_add(&S.cnt->point_pairs, ppairs);
   count_add(&S.cnt->visits[1], visits);
+  count_add(&S.cnt->cache_hits, hits);
 }
 
 // ---------------------------------------------------- full scan kernel ----
@@ -1026,7 +1178,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
   __shared__ double red_v[kBlock / kWave];
   __shared__ unsigned long long red_k[kBlock / kWave];
   __shared__ double red_b[kBlock / kWave];
-  long long evals = 0, ppairs = 0, visits = 0;
+  long long evals = 0, ppairs = 0, visits = 0, hits = 0;
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
     const int ti = list ? list[q] : q;
     const int t = S.term[ti];
@@ -1065,6 +1217,17 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
         pair_bounds<LINK, 0>(ct, lt, ht, cc, S.lo + (size_t)s * d, S.hi + (size_t)s * d, d, lb, ub);
         if (S.prune && lb > fmin(bound, bestv) * kSlack) continue;
         const long long cost = (long long)n_t * n_c;
+        if (cost > kInlinePairs && S.cache_mask) {
+          double v;
+          if (cache_find(S, pair_key(S.node[t], S.node[s]), v) == 1) {
+            ++hits;
+            if (better(v, key, bestv, bestk)) {
+              bestv = v;
+              bestk = key;
+            }
+            continue;
+          }
+        }
         if (LINK == kComplete && cost > kInlinePairs) comp_ub_refine(S, t, s, ct, cc, d, ub);
         if (cost <= kInlinePairs) {
           const int beg_c = S.cbeg[s];
@@ -1127,6 +1290,10 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
         if (s == t) continue;
         const int n_c = S.csize[s];
         if ((long long)n_t * n_c <= kInlinePairs) continue;
+        if (S.cache_mask) {
+          double v;
+          if (cache_find(S, pair_key(S.node[t], S.node[s]), v) == 1) continue;  // already counted
+        }
         if (S.prune) {
           double lb, ub;
           pair_bounds<LINK, 0>(ct, lt, ht, S.wcen + (size_t)s * d, S.lo + (size_t)s * d, S.hi + (size_t)s * d,
@@ -1152,6 +1319,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
   count_add(&S.cnt->cluster_evals, evals);
   count_add(&S.cnt->point_pairs, ppairs);
   count_add(&S.cnt->visits[1], visits);
+  count_add(&S.cnt->cache_hits, hits);
 }
 
 // ---------------------------------------------------------- pair tiles ----
@@ -1480,6 +1648,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_finish(State S, int link) {
       S.pr_v[p] = v;
       atomicMin(&S.t_min[S.pr_t[p]], pos_bits(v));
       ++evals;
+      if (S.cache_mask) cache_fill(S, pair_key(S.node[S.term[S.pr_t[p]]], S.node[S.pr_c[p]]), v);
     }
   }
   count_add(&S.cnt->cluster_evals, evals);
@@ -1499,6 +1668,30 @@ __global__ void k_pair_key(State S) {
       const int c = S.pr_c[p];
       atomicMin(&S.t_key[ti], make_key(S.cid[c], c));
     }
+  }
+}
+
+// Pairs another terminal evaluated this round: take the stored value.
+__global__ void k_pending_min(State S) {
+  const int np = S.cnt->n_pend;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
+    const int ti = S.pd_t[i], c = S.pd_c[i];
+    double v;
+    if (cache_find(S, pair_key(S.node[S.term[ti]], S.node[c]), v) != 1) {
+      S.cnt->nonfinite = 4;  // a claimed pair was not evaluated
+      continue;
+    }
+    atomicMin(&S.t_min[ti], pos_bits(v));
+  }
+}
+
+__global__ void k_pending_key(State S) {
+  const int np = S.cnt->n_pend;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
+    const int ti = S.pd_t[i], c = S.pd_c[i];
+    double v;
+    if (cache_find(S, pair_key(S.node[S.term[ti]], S.node[c]), v) == 1 && pos_bits(v) == S.t_min[ti])
+      atomicMin(&S.t_key[ti], make_key(S.cid[c], c));
   }
 }
 
@@ -1618,6 +1811,7 @@ __global__ void k_merge(State S, int base) {
       S.moff[b] = sa;
     }
     S.node[a] = n + r;
+    S.node2slot[n + r] = a;
     S.succ[a] = -1;
     S.succ_node[a] = -1;
     S.predd[a] = kInfBits;
@@ -1780,6 +1974,21 @@ void launch_emit(State &S, int nact, hipStream_t s, int *t_ovf) {
 
 }  // namespace
 
+void launch_cache_clear(State &S, unsigned long long *keys, unsigned long long *vals, unsigned long long mask,
+                        hipStream_t s) {
+  (void)S;
+  k_cache_clear<<<nblk((long long)mask + 1, 8192), kBlock, 0, s>>>(keys, vals, mask);
+}
+
+void launch_cache_rebuild(State &S, const unsigned long long *okeys, const unsigned long long *ovals,
+                          unsigned long long omask, hipStream_t s) {
+  k_cache_rebuild<<<nblk((long long)omask + 1, 8192), kBlock, 0, s>>>(S, okeys, ovals, omask);
+}
+
+void launch_cache_unclaim(State &S, hipStream_t s) {
+  if (S.cache_mask) k_cache_unclaim<<<nblk((long long)S.cache_mask + 1, 8192), kBlock, 0, s>>>(S);
+}
+
 hipError_t set_direction_table() {
   double t[2][kSupDirs];
   for (int k = 0; k < kSupDirs; ++k) {
@@ -1890,8 +2099,10 @@ void launch_pairs(State &S, int round, int npairs, long long work, hipStream_t s
     }
     k_pair_finish<<<nblk((long long)npairs * kWave, 4096), kBlock, 0, s>>>(S, S.linkage);
   }
+  if (S.cache_mask) k_pending_min<<<2048, kBlock, 0, s>>>(S);
   k_term_key_reset<<<nblk(S.n, 2048), kBlock, 0, s>>>(S);
   if (npairs > 0) k_pair_key<<<nblk(npairs, 2048), kBlock, 0, s>>>(S);
+  if (S.cache_mask) k_pending_key<<<2048, kBlock, 0, s>>>(S);
 }
 
 // Second half of a round: chains, R-NN pairs, merges, compaction.

@@ -44,7 +44,8 @@ class pc_merge(ctypes.Structure):
 
 class pc_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
-                ("prune", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("prune", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("cache_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class pc_stats(ctypes.Structure):
@@ -54,7 +55,9 @@ class pc_stats(ctypes.Structure):
                 ("overflow_queries", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("ms_init", ctypes.c_double), ("ms_rounds", ctypes.c_double),
                 ("ms_finalize", ctypes.c_double), ("kernel_ms", ctypes.c_double * 4),
-                ("kernel_launches", ctypes.c_int64 * 4), ("candidate_visits", ctypes.c_int64 * 4)]
+                ("kernel_launches", ctypes.c_int64 * 4), ("candidate_visits", ctypes.c_int64 * 4),
+                ("cache_hits", ctypes.c_int64), ("cache_inserts", ctypes.c_int64),
+                ("cache_fail", ctypes.c_int64)]
 
     KERNELS = ("ring_search", "block_search", "pair_tiles", "ring_emit")
 
@@ -142,9 +145,10 @@ class Context:
 
     def hac(self, points, n: int, d: int, linkage, out, *, points_on_device: bool,
             out_on_device: bool, stream=None, prune: bool = True, stats: bool = True,
-            timing: bool = False):
+            timing: bool = False, cache_slots: int = -1):
         """Raw call: ``points``/``out`` are integer addresses."""
-        opt = pc_options(ctypes.sizeof(pc_options), 0, 1 if prune else 0, 1 if timing else 0)
+        opt = pc_options(ctypes.sizeof(pc_options), 0, 1 if prune else 0, 1 if timing else 0,
+                         int(cache_slots), 0)
         st = pc_stats()
         st.struct_size = ctypes.sizeof(pc_stats)
         rc = self.lib.pc_hac(self.handle, ctypes.c_void_p(points), int(n), int(d),
@@ -166,7 +170,7 @@ def _ctx(device: int) -> Context:
 
 
 def hac_device(x, linkage, *, prune: bool = True, ctx: Context | None = None, stream=None,
-               timing: bool = False):
+               timing: bool = False, cache_slots: int = -1):
     """Cluster a CUDA (HIP) float32 tensor of shape (n, d) that lives on the GPU.
 
     Returns ``(rows, stats)``: ``rows`` is an int64 device tensor (n-1, 4)
@@ -184,7 +188,8 @@ def hac_device(x, linkage, *, prune: bool = True, ctx: Context | None = None, st
     if stream is None:
         stream = torch.cuda.current_stream(x.device).cuda_stream
     st = ctx.hac(x.data_ptr(), n, d, linkage, rows.data_ptr(), points_on_device=True,
-                 out_on_device=True, stream=stream, prune=prune, timing=timing)
+                 out_on_device=True, stream=stream, prune=prune, timing=timing,
+                 cache_slots=cache_slots)
     return rows[: n - 1], st
 
 
@@ -202,7 +207,8 @@ def rows_to_Z(rows) -> np.ndarray:
     return Z
 
 
-def hac(x, linkage, *, prune: bool = True, device: int = 0, return_stats: bool = False):
+def hac(x, linkage, *, prune: bool = True, device: int = 0, return_stats: bool = False,
+        cache_slots: int = -1):
     """Cluster points (numpy array or tensor, (n, d) float32) on the GPU.
 
     Returns the scipy-convention linkage matrix Z (float64, (n-1, 4)).
@@ -213,7 +219,7 @@ def hac(x, linkage, *, prune: bool = True, device: int = 0, return_stats: bool =
         xt = x.to(torch.float32)
     else:
         xt = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).to("cuda:%d" % device)
-    rows, st = hac_device(xt, linkage, prune=prune)
+    rows, st = hac_device(xt, linkage, prune=prune, cache_slots=cache_slots)
     torch.cuda.synchronize(xt.device)
     Z = rows_to_Z(rows)
     return (Z, st) if return_stats else Z

@@ -165,3 +165,26 @@ def test_overflow_paths(pc, link, monkeypatch):
     assert np.array_equal(Z0, Z1) and np.array_equal(Z0, Z2)
     Zo, _ = oracle.nnchain(x, link, threads=8)
     assert _trees.same_tree(Z0, Zo, 4000, rtol=RTOL[link])
+
+
+@pytest.mark.parametrize("link", ["complete", "average"])
+def test_cache_on_equals_off(pc, link, monkeypatch):
+    """The cluster-pair cache (Alg. 4, Sec. 5) only avoids recomputation: rows
+    are identical with it off, on, and squeezed into a tiny table."""
+    x = synth.blobs(6000, 2, 20, 0.02, 41)
+    Z0, s0 = pc.hac(x, link, cache_slots=0, return_stats=True)
+    Z1, s1 = pc.hac(x, link, cache_slots=64, return_stats=True)
+    assert s0["cache_hits"] == 0 and s1["cache_inserts"] > 0
+    assert np.array_equal(Z0, Z1)
+    monkeypatch.setenv("PC_TEST_CACHE_CAP", "512")
+    Z2 = pc.hac(x, link, cache_slots=64)
+    assert np.array_equal(Z0, Z2)
+    Zo, _ = oracle.nnchain(x, link, threads=8)
+    assert _trees.same_tree(Z0, Zo, 6000, rtol=RTOL[link])
+
+
+def test_cache_d10_average(pc):
+    x = synth.blobs(3000, 10, 30, 0.02, 42)
+    Z0 = pc.hac(x, "average", cache_slots=0)
+    Z1, st = pc.hac(x, "average", cache_slots=64, return_stats=True)
+    assert np.array_equal(Z0, Z1) and st["cache_hits"] > 0
