@@ -71,7 +71,7 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   S.hi = c.take<float>(pts ? n * d : 1);
   const bool comp = linkage == kComplete;
   S.ext = c.take<int>(comp && d <= kExtMaxDim ? n * 2 * d : 1);
-  S.crad = c.take<double>(comp ? n : 1);
+  S.crad = c.take<double>(pts ? n : 1);  // radius bounds: complete and average
   S.sup = c.take<int>(comp && d == 2 ? n * kSupDirs : 1);
   S.act = c.take<int>(n);
   S.act2 = c.take<int>(n);
@@ -92,6 +92,16 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   S.item_cen = c.take<double>(grid ? n * d : 1);
   S.item_lo = c.take<float>(grid && pts ? n * d : 1);
   S.item_hi = c.take<float>(grid && pts ? n * d : 1);
+  const bool gram = d >= kGramMinDim && d <= kGramMaxDim;
+  const int kp = d <= 16 ? 16 : (d <= 32 ? 32 : (d <= 64 ? 64 : 128));
+  S.gkp = kp;
+  S.g16 = c.take<_Float16>(gram ? n * kp : 1);
+  S.gnorm = c.take<double>(gram ? n : 1);
+  S.gorg = c.take<double>(gram ? d : 1);
+  S.gmin = c.take<unsigned long long>(gram ? d : 1);
+  S.gmax = c.take<unsigned long long>(gram ? d : 1);
+  S.gscale = c.take<double>(1);
+  S.term_pos = c.take<int>(gram ? n : 1);
   S.t_best = c.take<double>(n);
   S.t_key = c.take<unsigned long long>(n);
   S.t_beta = c.take<double>(n);
@@ -265,12 +275,13 @@ static pc_status grow_tiles(pc_context *ctx, State &S, long long cap) {
 }
 
 static pc_status grow_cand(pc_context *ctx, State &S, long long cap) {
-  const size_t per = 2 * sizeof(int) + sizeof(double);
+  const size_t per = 2 * sizeof(int) + 2 * sizeof(double);
   HIPCHK(grow(ctx->cand, (size_t)cap * per + 1024));
   const long long cc = (long long)((ctx->cand.bytes - 1024) / per);
   S.cand_cap = cc;
   S.cd_lb = (double *)ctx->cand.p;
-  S.cd_t = (int *)(S.cd_lb + cc);
+  S.cd_v = S.cd_lb + cc;
+  S.cd_t = (int *)(S.cd_v + cc);
   S.cd_c = S.cd_t + cc;
   return PC_OK;
 }
@@ -327,6 +338,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   S.linkage = linkage;
   S.prune = prune;
   S.timing = (opt && opt->timing) ? 1 : 0;
+  S.gram = (prune && d >= kGramMinDim && d <= kGramMaxDim) ? 1 : 0;
   S.tev = ctx->tev;
   S.xin = nullptr;  // set once the device copy of the points is known
   double kms[4] = {0, 0, 0, 0};
@@ -353,6 +365,11 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   {
     pc_status st = grow_part(ctx, S, 2LL * n + 64);
     if (st != PC_OK) return st;
+  }
+  if (linkage == kWard && S.gram) {
+    pc_status st = grow_cand(ctx, S, std::max<long long>(1 << 22, 4 * n));
+    if (st != PC_OK) return st;
+    if (const char *e = getenv("PC_TEST_CAND_CAP")) S.cand_cap = std::min<long long>(S.cand_cap, atoll(e));
   }
   if (linkage != kWard) {
     pc_status st = grow_pairs(ctx, S, std::max<long long>(1 << 20, 2 * n));
@@ -411,10 +428,27 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     bool need_pairs = false;
     launch_round(S, (int)rounds, nact, s, need_pairs);
     HIPCHK(hipGetLastError());
+    if (S.gram) {
+      // the candidate record must hold every candidate the bounds keep
+      HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int tries = 0; h.cand_overflow; ++tries) {
+        if (tries >= 3) return fail(PC_ERR_DEVICE, "candidate record overflow");
+        S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;
+        launch_cache_unclaim(S, s);
+        pc_status st = grow_cand(ctx, S, (long long)h.n_cand + h.n_cand / 2 + 1024);
+        if (st != PC_OK) return st;
+        launch_round(S, (int)rounds, nact, s, need_pairs);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+      }
+      if (!need_pairs) launch_gram_keys(S, s);  // Ward: every value is already in place
+    }
     if (need_pairs) {
       HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      if (h.cand_overflow) {
+      if (h.cand_overflow && !S.gram) {
         // this round: emit by re-walking the rings; later rounds: a larger record
         launch_emit_fallback(S, nact, s);
         HIPCHK(hipGetLastError());
@@ -440,6 +474,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
           HIPCHK(hipStreamSynchronize(s));
         }
         if (h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap) return fail(PC_ERR_DEVICE, "pair list overflow");
+        if (S.gram && h.cand_overflow) return fail(PC_ERR_DEVICE, "candidate record overflow");
       }
       const int np = h.n_pairs;
       launch_pairs_prefix(S, np, s);

@@ -19,6 +19,8 @@ constexpr int kTile = 64;          // point-pair tile edge for deferred evaluati
 constexpr int kChunk = 256;        // points per filter block (complete linkage)
 constexpr int kExtMaxDim = 4;      // extreme-point bounds kept up to this d
 constexpr int kSupDirs = 64;       // d == 2, complete: support points in 64 fixed directions
+constexpr int kGramMinDim = 4;     // Gram (MFMA) search from this d on
+constexpr int kGramMaxDim = 128;   // largest d of the Gram search (K = 128 in LDS)
 constexpr uint32_t kInfBits = 0x7f800000u;
 
 enum Linkage { kComplete = 0, kAverage = 1, kWard = 2 };
@@ -158,7 +160,18 @@ struct State {
   // large candidates recorded by the bound pass (terminal index, slot, lower bound)
   int *cd_t, *cd_c;
   double *cd_lb;
+  double *cd_v;         // Gram search: exact value of a recorded candidate (NaN if deferred)
   long long cand_cap;
+  // Gram search (d >= kGramMinDim): FP16 copies of the active centroids,
+  // recentred on gorg and scaled by gscale, with FP64 norms of the rounded values
+  int gram;             // 1: this call searches with MFMA Gram tiles
+  int gkp;              // padded K (multiple of 16)
+  _Float16 *g16;        // n x gkp, in active-list order
+  double *gnorm;
+  double *gorg;         // d
+  unsigned long long *gmin, *gmax;  // per-dimension ordered bits of the centroid range
+  double *gscale;       // 1 value
+  int *term_pos;        // active-list index of each terminal
   double *tile_v;
   long long pair_cap, tile_cap;
   int cell_cap;
@@ -185,6 +198,7 @@ void launch_check_finite(const float *x, long long count, Counters *cnt, hipStre
 void launch_init(State &S, const float *x, hipStream_t s);
 void launch_round(State &S, int round, int nact_host, hipStream_t s, bool &need_pairs);
 void launch_emit_fallback(State &S, int nact_host, hipStream_t s);
+void launch_gram_keys(State &S, hipStream_t s);
 void launch_cache_clear(State &S, unsigned long long *keys, unsigned long long *vals,
                         unsigned long long mask, hipStream_t s);
 void launch_cache_rebuild(State &S, const unsigned long long *okeys, const unsigned long long *ovals,

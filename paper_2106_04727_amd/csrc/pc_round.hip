@@ -188,8 +188,8 @@ __global__ void k_init_slots(State S, const float *x, const unsigned *perm) {
     S.wsum[(size_t)s * d + k] = (double)v;
     S.wcen[(size_t)s * d + k] = (double)v;
   }
+  if (S.linkage != kWard) S.crad[s] = 0.0;
   if (S.linkage == kComplete) {
-    S.crad[s] = 0.0;
     if (d == 2)
       for (int k = 0; k < kSupDirs; ++k) S.sup[(size_t)s * kSupDirs + k] = p;
     if (d <= kExtMaxDim)
@@ -1695,6 +1695,345 @@ __global__ void k_pending_key(State S) {
   }
 }
 
+// ------------------------------------------------------------ Gram search --
+// For d >= kGramMinDim the centroid grid prunes poorly, so every terminal is
+// compared with every active cluster through MFMA Gram tiles, with exact FP64
+// refinement of every candidate the rounding bound cannot rule out:
+//   * centroids are recentred on the middle of their range, scaled into
+//     [-1, 1] and rounded to FP16; the norms are FP64 norms of the rounded
+//     vectors, so d2~ = |x~|^2 + |y~|^2 - 2 x~.y~ errs only by the rounding of
+//     the coordinates (which scales with the distance) and by the FP32
+//     accumulation inside the MFMA (gamma_K |x~||y~|);
+//   * pass 0: every terminal's smallest upper bound U on its key over all
+//     candidates (centroid distance plus radii bounds complete and average
+//     linkage; Table 1 for Ward);
+//   * pass 1: every candidate whose lower bound (the centroid distance bounds
+//     complete and average from below, Sec. 4.2-4.3) does not exceed U is
+//     recorded and evaluated exactly afterwards.
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float float16v __attribute__((ext_vector_type(16)));
+constexpr int kGT = 64;                                    // block tile: 64 terminals x 64 candidates
+constexpr double kU16 = 1.0 / 2048.0 + 1.0 / 16777216.0;  // FP16 rounding (via FP32)
+constexpr double kEta16 = 1.0 / 33554432.0;                // half the FP16 subnormal spacing
+
+// per-dimension range of the active centroids: a wave per item, lanes over dims
+__global__ void k_gram_range(State S) {
+  const int nact = S.cnt->n_act, d = S.d;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, nw = (gridDim.x * blockDim.x) / kWave;
+  unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
+  for (int i = w0; i < nact; i += nw) {
+    const double *c = S.wcen + (size_t)S.act[i] * d;
+    for (int j = 0; j < 2; ++j) {
+      const int k = lane + j * kWave;
+      if (k < d) {
+        const unsigned long long b = ordered_bits(c[k]);
+        lo[j] = b < lo[j] ? b : lo[j];
+        hi[j] = b > hi[j] ? b : hi[j];
+      }
+    }
+  }
+  for (int j = 0; j < 2; ++j) {
+    const int k = lane + j * kWave;
+    if (k < d && lo[j] != ~0ull) {
+      atomicMin(&S.gmin[k], lo[j]);
+      atomicMax(&S.gmax[k], hi[j]);
+    }
+  }
+}
+
+__global__ void k_gram_setup(State S) {
+  const int k = threadIdx.x;
+  __shared__ double rr[kGramMaxDim];
+  double r = 0.0;
+  if (k < S.d) {
+    const double lo = from_ordered_bits(S.gmin[k]), hi = from_ordered_bits(S.gmax[k]);
+    S.gorg[k] = 0.5 * (lo + hi);
+    r = 0.5 * (hi - lo);
+  }
+  rr[k] = r;
+  __syncthreads();
+  if (k == 0) {
+    double m = 0.0;
+    for (int j = 0; j < S.d; ++j) m = rr[j] > m ? rr[j] : m;
+    *S.gscale = m > 0.0 ? 1.0 / m : 1.0;
+  }
+}
+
+__global__ void k_gram_reset(State S) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < S.d) {
+    S.gmin[k] = ~0ull;
+    S.gmax[k] = 0ull;
+  }
+}
+
+// FP16 copy of every active centroid (active-list order) and the FP64 norm of
+// the rounded vector: a wave per item, lanes over dims
+__global__ void k_gram_prep(State S) {
+  const int nact = S.cnt->n_act, d = S.d, kp = S.gkp;
+  const double sc = *S.gscale;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, nw = (gridDim.x * blockDim.x) / kWave;
+  for (int i = w0; i < nact; i += nw) {
+    const double *c = S.wcen + (size_t)S.act[i] * d;
+    double nrm = 0.0;
+    for (int k = lane; k < kp; k += kWave) {
+      _Float16 h = (_Float16)0.0f;
+      if (k < d) h = (_Float16)(float)((c[k] - S.gorg[k]) * sc);
+      S.g16[(size_t)i * kp + k] = h;
+      const double hv = (double)(float)h;
+      nrm += hv * hv;
+    }
+    nrm = wave_sum(nrm);
+    if (lane == 0) S.gnorm[i] = nrm;
+  }
+}
+
+__global__ void k_term_pos(State S) {
+  const int nact = S.cnt->n_act;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nact; i += gridDim.x * blockDim.x)
+    if (S.flags[i]) S.term_pos[S.scan[i]] = i;
+}
+
+template <int LINK>
+__global__ void k_gram_init(State S, int *t_ovf) {
+  const int nterm = S.cnt->n_term;
+  for (int ti = blockIdx.x * blockDim.x + threadIdx.x; ti < nterm; ti += gridDim.x * blockDim.x) {
+    S.t_best[ti] = INFINITY;
+    S.t_key[ti] = kNoKey;
+    S.t_min[ti] = pos_bits(INFINITY);
+    S.t_beta[ti] = beta_key<LINK>(S.predd[S.term[ti]]);
+    t_ovf[ti] = 0;
+  }
+}
+
+// Rounding bound of d2~ in scaled units (see the comment above).
+__device__ __forceinline__ void gram_bounds(double d2h, double nq, double nc, int d, int kp, double &lo2,
+                                            double &hi2) {
+  const double sq = sqrt(nq), sn = sqrt(nc);
+  const double delta = kU16 * (sq + sn) * (1.0 + 4.0 * kU16) + 2.0 * sqrt((double)d) * kEta16;
+  const double gk = (double)kp * 6.0e-8;  // FP32 accumulation over kp terms
+  const double a = 2.0 * delta;
+  const double b = delta * delta + 2.02 * gk * sq * sn + 4e-16 * (nq + nc);
+  const double dm = d2h > 0.0 ? d2h : 0.0;
+  const double dup = 0.5 * (a + sqrt(a * a + 4.0 * (dm + b)));
+  const double e = 1.05 * (a * dup + b);
+  lo2 = d2h - e > 0.0 ? d2h - e : 0.0;
+  hi2 = dm + e;
+}
+
+template <int LINK>
+__device__ __forceinline__ void gram_keys(double lo2, double hi2, double sc, int nq, int nc, double rq, double rc,
+                                          double &klo, double &khi) {
+  const double is2 = 1.0 / (sc * sc);
+  if (LINK == kWard) {
+    const double w = (2.0 * (double)nq * (double)nc) / ((double)nq + (double)nc);
+    klo = w * lo2 * is2 * (1.0 - 1e-12);
+    khi = w * hi2 * is2 * (1.0 + 1e-12);
+  } else if (LINK == kComplete) {
+    klo = lo2 * is2 * (1.0 - 1e-12);
+    const double u = sqrt(hi2 * is2) + rq + rc;
+    khi = u * u * (1.0 + 1e-12);
+  } else {
+    klo = sqrt(lo2 * is2) * (1.0 - 1e-12);
+    khi = (sqrt(hi2 * is2) + rq + rc) * (1.0 + 1e-12);
+  }
+}
+
+template <int LINK, int KP, int PASS>
+__global__ __launch_bounds__(kBlock) void k_gram(State S) {
+  __shared__ __attribute__((aligned(16))) _Float16 sq[kGT][KP];
+  __shared__ __attribute__((aligned(16))) _Float16 sc[kGT][KP];
+  __shared__ double qn[kGT], cn[kGT], qr[kGT], cr[kGT], qb[kGT];
+  __shared__ int qs[kGT], cs[kGT], qz[kGT], cz[kGT], qt[kGT];
+  __shared__ double rmin[4][32];
+  const int nterm = S.cnt->n_term, nact = S.cnt->n_act;
+  const int q0 = blockIdx.x * kGT;
+  if (q0 >= nterm) return;  // uniform per block
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const double scale = *S.gscale;
+  const int d = S.d;
+  // query tile
+  constexpr int CH = KP / 8;  // 16-byte chunks per row
+  for (int j = threadIdx.x; j < kGT * CH; j += kBlock) {
+    const int r = j / CH, c8 = j % CH;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (q0 + r < nterm) v = *(const uint4 *)(S.g16 + (size_t)S.term_pos[q0 + r] * KP + c8 * 8);
+    *(uint4 *)&sq[r][c8 * 8] = v;
+  }
+  if (threadIdx.x < kGT) {
+    const int r = threadIdx.x, ti = q0 + r;
+    if (ti < nterm) {
+      const int t = S.term[ti], pi = S.term_pos[ti];
+      qs[r] = t;
+      qt[r] = ti;
+      qn[r] = S.gnorm[pi];
+      qz[r] = S.csize[t];
+      qr[r] = LINK != kWard ? S.crad[t] : 0.0;
+      qb[r] = PASS == 1 ? S.t_beta[ti] * kSlack : 0.0;
+    } else {
+      qs[r] = -1;
+      qt[r] = -1;
+    }
+  }
+  double run[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) run[i] = INFINITY;
+  long long pairs = 0;
+  for (int c0 = blockIdx.y * kGT; c0 < nact; c0 += gridDim.y * kGT) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < kGT * CH; j += kBlock) {
+      const int r = j / CH, c8 = j % CH;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (c0 + r < nact) v = *(const uint4 *)(S.g16 + (size_t)(c0 + r) * KP + c8 * 8);
+      *(uint4 *)&sc[r][c8 * 8] = v;
+    }
+    if (threadIdx.x < kGT) {
+      const int r = threadIdx.x, ci = c0 + r;
+      if (ci < nact) {
+        const int sl = S.act[ci];
+        cs[r] = sl;
+        cn[r] = S.gnorm[ci];
+        cz[r] = S.csize[sl];
+        cr[r] = LINK != kWard ? S.crad[sl] : 0.0;
+      } else {
+        cs[r] = -2;
+      }
+    }
+    __syncthreads();
+    float16v acc = {};
+#pragma unroll
+    for (int kk = 0; kk < KP; kk += 16) {
+      const half8 a = *(const half8 *)&sq[wr + (lane & 31)][kk + (lane >> 5) * 8];
+      const half8 b = *(const half8 *)&sc[wc + (lane & 31)][kk + (lane >> 5) * 8];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
+    }
+    const int col = wc + (lane & 31);
+    const int cslot = cs[col];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = wr + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+      const int qslot = qs[row];
+      if (qslot < 0 || cslot < 0 || qslot == cslot) continue;
+      const double d2h = qn[row] + cn[col] - 2.0 * (double)acc[i];
+      double lo2, hi2, klo, khi;
+      gram_bounds(d2h, qn[row], cn[col], d, KP, lo2, hi2);
+      gram_keys<LINK>(lo2, hi2, scale, qz[row], cz[col], qr[row], cr[col], klo, khi);
+      ++pairs;
+      if (PASS == 0) {
+        run[i] = khi < run[i] ? khi : run[i];
+      } else if (klo <= qb[row]) {
+        const int k = atomicAdd(&S.cnt->n_cand, 1);
+        if (k < S.cand_cap) {
+          S.cd_t[k] = qt[row];
+          S.cd_c[k] = cslot;
+          S.cd_lb[k] = klo;
+        } else {
+          S.cnt->cand_overflow = 1;
+        }
+      }
+    }
+  }
+  if (PASS == 0) {
+    // row minima: reduce over the 32 lanes holding one row, then over the two
+    // wavefronts that share the rows
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double v = run[i];
+      for (int o = 16; o > 0; o >>= 1) {
+        const double u = __shfl_xor(v, o, kWave);
+        v = u < v ? u : v;
+      }
+      run[i] = v;
+    }
+    if ((lane & 31) == 0)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) rmin[w][(i >> 2) * 8 + (lane >> 5) * 4 + (i & 3)] = run[i];
+    __syncthreads();
+    if (threadIdx.x < kGT) {
+      const int r = threadIdx.x, wq = (r >> 5) * 2;
+      const double v = fmin(rmin[wq][r & 31], rmin[wq + 1][r & 31]);
+      if (qt[r] >= 0 && v < INFINITY) atomicMin((unsigned long long *)&S.t_beta[qt[r]], pos_bits(v));
+    }
+  }
+  if (PASS == 0) count_add(&S.cnt->visits[0], pairs);
+  else count_add(&S.cnt->visits[3], pairs);
+}
+
+// Recorded candidates: exact FP64 value (Ward, small complete/average pairs,
+// cache hits) or a claim on the pair for the tile pass.
+template <int LINK>
+__global__ void k_gram_exact(State S) {
+  if (S.cnt->cand_overflow) return;  // the round is redone with a larger record
+  const int nc = S.cnt->n_cand, d = S.d;
+  long long evals = 0, ppairs = 0, hits = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+    const int ti = S.cd_t[i], c = S.cd_c[i];
+    S.cd_v[i] = NAN;
+    if (S.cd_lb[i] > S.t_beta[ti] * kSlack) continue;
+    const int t = S.term[ti];
+    double v;
+    if (LINK == kWard) {
+      v = ward_key<0>(S.wcen + (size_t)t * d, (double)S.csize[t], S.wcen + (size_t)c * d, (double)S.csize[c], d);
+      ++evals;
+    } else {
+      const int nt = S.csize[t], ncs = S.csize[c];
+      const long long cost = (long long)nt * ncs;
+      if (cost <= kInlinePairs) {
+        v = (S.cid[c] < S.cid[t]) ? pair_exact_inline<LINK>(S.px, d, S.cbeg[c], ncs, S.cbeg[t], nt)
+                                  : pair_exact_inline<LINK>(S.px, d, S.cbeg[t], nt, S.cbeg[c], ncs);
+        ++evals;
+        ppairs += cost;
+      } else {
+        const unsigned long long pk = pair_key(S.node[t], S.node[c]);
+        if (S.cache_mask && cache_find(S, pk, v) == 1) {
+          ++hits;
+        } else {
+          if (S.cache_mask && cache_claim(S, pk) == 2) {
+            const int q = atomicAdd(&S.cnt->n_pend, 1);
+            if (q < S.pair_cap) {
+              S.pd_t[q] = ti;
+              S.pd_c[q] = c;
+            } else {
+              S.cnt->pair_overflow = 1;
+            }
+            continue;
+          }
+          const int p = atomicAdd(&S.cnt->n_pairs, 1);
+          if (p < S.pair_cap) {
+            S.pr_t[p] = ti;
+            S.pr_c[p] = c;
+            S.pr_v[p] = -1.0;
+          } else {
+            S.cnt->pair_overflow = 1;
+          }
+          continue;
+        }
+      }
+    }
+    S.cd_v[i] = v;
+    atomicMin(&S.t_min[ti], pos_bits(v));
+  }
+  count_add(&S.cnt->cluster_evals, evals);
+  count_add(&S.cnt->point_pairs, ppairs);
+  count_add(&S.cnt->cache_hits, hits);
+}
+
+// After every value of the round is in t_min: the lowest cluster ID among the
+// recorded candidates that reach it.
+__global__ void k_gram_key(State S) {
+  if (S.cnt->cand_overflow) return;
+  const int nc = S.cnt->n_cand;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+    const double v = S.cd_v[i];
+    if (!(v >= 0.0)) continue;
+    const int ti = S.cd_t[i], c = S.cd_c[i];
+    if (pos_bits(v) == S.t_min[ti]) atomicMin(&S.t_key[ti], make_key(S.cid[c], c));
+  }
+}
+
 // ---------------------------------------------------------------- chain --
 // succ := nearest neighbour; WriteMin of the distance into the neighbour's
 // predecessor slot (Alg. 1 chain update, the neighbour's pred is written).
@@ -1709,7 +2048,7 @@ __global__ void k_chain(State S) {
       continue;
     }
     const int u = (int)(key & 0xffffffffu);
-    const double v = S.linkage == kWard ? S.t_best[ti] : pos_from_bits(S.t_min[ti]);
+    const double v = (S.linkage == kWard && !S.gram) ? S.t_best[ti] : pos_from_bits(S.t_min[ti]);
     const double h = key_to_height(S.linkage, v);
     S.succ[t] = u;
     S.succ_node[t] = S.node[u];
@@ -1776,7 +2115,7 @@ __global__ void k_merge(State S, int base) {
     S.eff[a] = e;
     const int ns = sa + sb;
     S.csize[a] = ns;
-    if (S.linkage == kComplete) {
+    if (S.linkage != kWard) {
       // radius bound of the union: max over children of |c_new - c_child| + r_child
       // (old centroids are still in place here)
       double da = 0.0, db = 0.0;
@@ -1788,6 +2127,8 @@ __global__ void k_merge(State S, int base) {
       }
       const double ra = sqrt(da) + S.crad[a], rb = sqrt(db) + S.crad[b];
       S.crad[a] = (ra > rb ? ra : rb) * (1.0 + 1e-12);
+    }
+    if (S.linkage == kComplete) {
       if (d <= kExtMaxDim)
         for (int k = 0; k < d; ++k) {
           int *ea = S.ext + (size_t)a * 2 * d, *eb = S.ext + (size_t)b * 2 * d;
@@ -1972,7 +2313,40 @@ void launch_emit(State &S, int nact, hipStream_t s, int *t_ovf) {
   }
 }
 
+template <int LINK, int KP>
+void launch_gram_kp(State &S, int nact, hipStream_t s) {
+  const int gx = (nact + kGT - 1) / kGT;
+  int gy = 4096 / gx;
+  const int maxy = (nact + kGT - 1) / kGT;
+  gy = gy < 1 ? 1 : (gy > maxy ? maxy : gy);
+  tmark(S, 0, false, s);
+  k_gram<LINK, KP, 0><<<dim3(gx, gy), kBlock, 0, s>>>(S);
+  tmark(S, 0, true, s);
+  tmark(S, 3, false, s);
+  k_gram<LINK, KP, 1><<<dim3(gx, gy), kBlock, 0, s>>>(S);
+  k_gram_exact<LINK><<<2048, kBlock, 0, s>>>(S);
+  tmark(S, 3, true, s);
+}
+
+template <int LINK>
+void launch_gram(State &S, int nact, hipStream_t s, int *t_ovf) {
+  const int gb = nblk(nact, 2048);
+  k_gram_reset<<<1, kGramMaxDim, 0, s>>>(S);
+  k_gram_range<<<nblk((long long)nact * kWave, 1024), kBlock, 0, s>>>(S);
+  k_gram_setup<<<1, kGramMaxDim, 0, s>>>(S);
+  k_gram_prep<<<nblk((long long)nact * kWave, 4096), kBlock, 0, s>>>(S);
+  k_gram_init<LINK><<<gb, kBlock, 0, s>>>(S, t_ovf);
+  switch (S.gkp) {
+  case 16: launch_gram_kp<LINK, 16>(S, nact, s); break;
+  case 32: launch_gram_kp<LINK, 32>(S, nact, s); break;
+  case 64: launch_gram_kp<LINK, 64>(S, nact, s); break;
+  default: launch_gram_kp<LINK, 128>(S, nact, s); break;
+  }
+}
+
 }  // namespace
+
+void launch_gram_keys(State &S, hipStream_t s) { k_gram_key<<<2048, kBlock, 0, s>>>(S); }
 
 void launch_cache_clear(State &S, unsigned long long *keys, unsigned long long *vals, unsigned long long mask,
                         hipStream_t s) {
@@ -2022,7 +2396,7 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
   k_act_pass<<<gb, kBlock, 0, s>>>(S, round);
   scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, &S.cnt->n_term, S.part, s);
   k_scatter_flagged<<<gb, kBlock, 0, s>>>(S.act, S.flags, S.scan, &S.cnt->n_act, S.term);
-  if (S.d <= kGridMaxDim && S.prune) {
+  if (S.d <= kGridMaxDim && S.prune && !S.gram) {
     k_grid_params<<<1, 1, 0, s>>>(S, S.cell_cap);
     k_zero_cells<<<nblk(nact + 1, 2048), kBlock, 0, s>>>(S);
     k_cell_count<<<gb, kBlock, 0, s>>>(S);
@@ -2032,6 +2406,15 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
   }
   int *t_ovf = S.cell_rank;  // per-terminal hand-off flags (cell ranks are no longer needed)
   need_pairs = false;
+  if (S.gram) {
+    k_term_pos<<<gb, kBlock, 0, s>>>(S);
+    switch (S.linkage) {
+    case kWard: launch_gram<kWard>(S, nact, s, t_ovf); break;
+    case kComplete: launch_gram<kComplete>(S, nact, s, t_ovf); need_pairs = true; break;
+    default: launch_gram<kAverage>(S, nact, s, t_ovf); need_pairs = true; break;
+    }
+    return;
+  }
   switch (S.linkage) {
   case kWard: launch_search<kWard>(S, nact, s, t_ovf); break;
   case kComplete:
@@ -2103,6 +2486,7 @@ void launch_pairs(State &S, int round, int npairs, long long work, hipStream_t s
   k_term_key_reset<<<nblk(S.n, 2048), kBlock, 0, s>>>(S);
   if (npairs > 0) k_pair_key<<<nblk(npairs, 2048), kBlock, 0, s>>>(S);
   if (S.cache_mask) k_pending_key<<<2048, kBlock, 0, s>>>(S);
+  if (S.gram) k_gram_key<<<2048, kBlock, 0, s>>>(S);
 }
 
 // Second half of a round: chains, R-NN pairs, merges, compaction.

@@ -65,9 +65,15 @@ def test_fig1_worked_example(pc):
 @pytest.mark.parametrize("n,d,kind,seed", [
     (2, 2, "u", 1), (3, 2, "u", 2), (64, 2, "u", 3), (257, 1, "u", 4), (1000, 2, "b", 5),
     (2000, 3, "u", 6), (3000, 10, "b", 7), (700, 16, "u", 8), (500, 40, "b", 9),
+    (1500, 4, "u", 10), (2000, 64, "b", 11), (2500, 128, "s", 12), (800, 100, "s", 13),
 ])
 def test_parity_small(pc, link, n, d, kind, seed):
-    x = synth.uniform(n, d, seed) if kind == "u" else synth.blobs(n, d, 8, 0.03, seed)
+    if kind == "u":
+        x = synth.uniform(n, d, seed)
+    elif kind == "b":
+        x = synth.blobs(n, d, 8, 0.03, seed)
+    else:
+        x = synth.sphere_blobs(n, d, 25, 0.1, seed)
     _, cert = oracle.nnchain(x, link, threads=8)
     if cert["min_gap"] < 1e-10:
         pytest.skip("input not certified tie-free")
@@ -188,3 +194,14 @@ def test_cache_d10_average(pc):
     Z0 = pc.hac(x, "average", cache_slots=0)
     Z1, st = pc.hac(x, "average", cache_slots=64, return_stats=True)
     assert np.array_equal(Z0, Z1) and st["cache_hits"] > 0
+
+
+@pytest.mark.parametrize("link", LINKS)
+def test_gram_record_overflow(pc, link, monkeypatch):
+    """d >= 4 searches with MFMA Gram tiles; a tiny candidate record forces
+    the regrow-and-redo path, which must not change the rows."""
+    x = synth.blobs(3000, 10, 20, 0.03, 51)
+    Z0 = pc.hac(x, link)
+    monkeypatch.setenv("PC_TEST_CAND_CAP", "64")
+    Z1 = pc.hac(x, link)
+    assert np.array_equal(Z0, Z1)
