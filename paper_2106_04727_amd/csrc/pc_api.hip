@@ -72,6 +72,7 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   const bool comp = linkage == kComplete;
   S.ext = c.take<int>(comp && d <= kExtMaxDim ? n * 2 * d : 1);
   S.crad = c.take<double>(pts ? n : 1);  // radius bounds: complete and average
+  S.cvar = c.take<double>(pts ? n : 1);
   S.sup = c.take<int>(comp && d == 2 ? n * kSupDirs : 1);
   S.act = c.take<int>(n);
   S.act2 = c.take<int>(n);
@@ -231,6 +232,10 @@ size_t pc_hac_workspace_bytes(int64_t n, int32_t d, int32_t linkage, const pc_op
   return bytes;
 }
 
+// Largest candidate record / pair list a round may use (entries). Beyond it a
+// call fails with PC_ERR_OUT_OF_MEMORY instead of growing without bound.
+constexpr long long kMaxRecord = 1LL << 30;
+
 // Scan partials: one per 1024 elements of the longest scan of the call.
 static pc_status grow_part(pc_context *ctx, State &S, long long longest_scan) {
   const long long need = longest_scan / 1024 + 1024;
@@ -241,6 +246,7 @@ static pc_status grow_part(pc_context *ctx, State &S, long long longest_scan) {
 }
 
 static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
+  if (cap > kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round needs more than 2^30 cluster pairs");
   // per pair: tile prefix (i64), chunk prefix (i64), value (f64), t, c, kR, kS,
   // pending t, pending c (i32)
   const size_t per = 3 * sizeof(long long) + 6 * sizeof(int);
@@ -261,6 +267,7 @@ static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
 }
 
 static pc_status grow_fidx(pc_context *ctx, State &S, long long cap) {
+  if (cap > 8 * kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round's pair filter needs too many points");
   HIPCHK(grow(ctx->fidx, (size_t)cap * sizeof(int)));
   S.fidx = (int *)ctx->fidx.p;
   S.fidx_cap = (long long)(ctx->fidx.bytes / sizeof(int));
@@ -275,6 +282,7 @@ static pc_status grow_tiles(pc_context *ctx, State &S, long long cap) {
 }
 
 static pc_status grow_cand(pc_context *ctx, State &S, long long cap) {
+  if (cap > kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round needs more than 2^30 recorded candidates");
   const size_t per = 2 * sizeof(int) + 2 * sizeof(double);
   HIPCHK(grow(ctx->cand, (size_t)cap * per + 1024));
   const long long cc = (long long)((ctx->cand.bytes - 1024) / per);
@@ -419,6 +427,9 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   HIPCHK(hipEventRecord(ctx->ev[1], s));
 
   const bool debug = getenv("PC_DEBUG") != nullptr;
+  long long gram_batch = 0;  // terminals per Gram batch (0: all), kept across rounds
+  // test hook: small batches exercise the batch loop on small inputs
+  if (const char *e = getenv("PC_TEST_GRAM_BATCH")) gram_batch = std::max<long long>(1, atoll(e));
   int nact = (int)n;
   int merges = 0;
   long long rounds = 0, terms = 0, ovfq = 0;
@@ -426,57 +437,12 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   while (nact > 1) {
     if (rounds > n) return fail(PC_ERR_DEVICE, "round loop did not converge");
     bool need_pairs = false;
+    S.tb0 = 0;
+    S.tb1 = 0x7fffffff;
     launch_round(S, (int)rounds, nact, s, need_pairs);
     HIPCHK(hipGetLastError());
-    if (S.gram) {
-      // the candidate record must hold every candidate the bounds keep
-      HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      for (int tries = 0; h.cand_overflow; ++tries) {
-        if (tries >= 3) return fail(PC_ERR_DEVICE, "candidate record overflow");
-        S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;
-        launch_cache_unclaim(S, s);
-        pc_status st = grow_cand(ctx, S, (long long)h.n_cand + h.n_cand / 2 + 1024);
-        if (st != PC_OK) return st;
-        launch_round(S, (int)rounds, nact, s, need_pairs);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-      }
-      if (!need_pairs) launch_gram_keys(S, s);  // Ward: every value is already in place
-    }
-    if (need_pairs) {
-      HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      if (h.cand_overflow && !S.gram) {
-        // this round: emit by re-walking the rings; later rounds: a larger record
-        launch_emit_fallback(S, nact, s);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        pc_status st = grow_cand(ctx, S, (long long)h.n_cand + h.n_cand / 2 + 1024);
-        if (st != PC_OK) return st;
-      }
-      if (h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap) {
-        S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;  // the round is redone
-        launch_cache_unclaim(S, s);
-        const long long want = std::max<long long>(h.n_pairs, h.n_pend);
-        pc_status st = grow_pairs(ctx, S, want + want / 2 + 1024);
-        if (st != PC_OK) return st;
-        launch_round(S, (int)rounds, nact, s, need_pairs);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (h.cand_overflow) {
-          launch_emit_fallback(S, nact, s);
-          HIPCHK(hipGetLastError());
-          HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-          HIPCHK(hipStreamSynchronize(s));
-        }
-        if (h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap) return fail(PC_ERR_DEVICE, "pair list overflow");
-        if (S.gram && h.cand_overflow) return fail(PC_ERR_DEVICE, "candidate record overflow");
-      }
-      const int np = h.n_pairs;
+    // evaluate the emitted pairs of the current terminals (tiles), then their keys
+    auto pairs_pipeline = [&](int np) -> pc_status {
       launch_pairs_prefix(S, np, s);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
@@ -496,13 +462,105 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
         }
       }
       launch_pairs(S, (int)rounds, np, work, s);
+      HIPCHK(hipGetLastError());
       if (debug) {
         HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        fprintf(stderr, "[parchain] round %lld nact %d nterm %d novf %d pairs %d work %lld tiles %lld pp %lld\n",
-                rounds, nact, h.n_term, h.n_ovf, np, work, h.n_tiles, h.point_pairs);
+        fprintf(stderr, "[parchain] round %lld nact %d nterm %d batch [%d,%d) pairs %d work %lld tiles %lld pp %lld\n",
+                rounds, nact, h.n_term, S.tb0, S.tb1 == 0x7fffffff ? h.n_term : S.tb1, np, work, h.n_tiles,
+                h.point_pairs);
       }
-      HIPCHK(hipGetLastError());
+      return PC_OK;
+    };
+    if (S.gram) {
+      // Gram search: terminals in batches, each with a bounded candidate record
+      HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const int nterm = h.n_term;
+      long long tb = gram_batch > 0 ? std::min<long long>(gram_batch, nterm) : nterm;
+      for (int t0 = 0; t0 < nterm;) {
+        const int t1 = (int)std::min<long long>(nterm, t0 + tb);
+        S.tb0 = t0;
+        S.tb1 = t1;
+        launch_gram_batch(S, nact, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const bool pover = h.pair_overflow || h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap;
+        if (h.cand_overflow || pover) {
+          // redo this batch: larger buffers while they stay within the limit,
+          // otherwise fewer terminals per batch
+          S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;
+          launch_cache_unclaim(S, s);
+          bool shrink = false;
+          if (h.cand_overflow) {
+            const long long want = h.n_cand + h.n_cand / 2 + 1024;
+            if (want <= kMaxRecord) {
+              pc_status st = grow_cand(ctx, S, want);
+              if (st != PC_OK) return st;
+            } else {
+              shrink = true;
+            }
+          }
+          if (pover) {
+            const long long want = std::max<long long>(h.n_pairs, h.n_pend) * 3 / 2 + 1024;
+            if (want <= kMaxRecord) {
+              pc_status st = grow_pairs(ctx, S, want);
+              if (st != PC_OK) return st;
+            } else {
+              shrink = true;
+            }
+          }
+          if (shrink) {
+            if (t1 - t0 <= 1) return fail(PC_ERR_OUT_OF_MEMORY, "one terminal exceeds the candidate limit");
+            tb = std::max<long long>(1, (t1 - t0) / 4);
+            gram_batch = tb;
+          }
+          continue;
+        }
+        if (linkage == kWard) {
+          launch_gram_keys(S, s);
+        } else {
+          pc_status st = pairs_pipeline((int)h.n_pairs);
+          if (st != PC_OK) return st;
+        }
+        t0 = t1;
+      }
+      S.tb0 = 0;
+      S.tb1 = 0x7fffffff;
+    } else if (need_pairs) {
+      HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (h.cand_overflow) {
+        // this round: emit by re-walking the rings; later rounds: a larger record
+        launch_emit_fallback(S, nact, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const long long want = std::min<long long>(h.n_cand + h.n_cand / 2 + 1024, kMaxRecord);
+        pc_status st = grow_cand(ctx, S, want);
+        if (st != PC_OK) return st;
+      }
+      if (h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap) {
+        S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;  // the round is redone
+        launch_cache_unclaim(S, s);
+        const long long want = std::max<long long>(h.n_pairs, h.n_pend);
+        pc_status st = grow_pairs(ctx, S, want + want / 2 + 1024);
+        if (st != PC_OK) return st;
+        launch_round(S, (int)rounds, nact, s, need_pairs);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h.cand_overflow) {
+          launch_emit_fallback(S, nact, s);
+          HIPCHK(hipGetLastError());
+          HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+        }
+        if (h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap) return fail(PC_ERR_DEVICE, "pair list overflow");
+      }
+      pc_status st = pairs_pipeline((int)h.n_pairs);
+      if (st != PC_OK) return st;
     }
     launch_round_tail(S, (int)rounds, nact, merges, s);
     HIPCHK(hipGetLastError());

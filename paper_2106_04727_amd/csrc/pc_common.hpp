@@ -26,6 +26,10 @@ constexpr uint32_t kInfBits = 0x7f800000u;
 enum Linkage { kComplete = 0, kAverage = 1, kWard = 2 };
 
 // ---------------------------------------------------------------- helpers --
+// Reserve one slot of a 64-bit append counter; returns the slot index.
+__device__ __forceinline__ long long append_slot(long long *counter) {
+  return (long long)atomicAdd((unsigned long long *)counter, 1ull);
+}
 __device__ __forceinline__ unsigned long long ordered_bits(double v) {
   // monotone map of doubles to unsigned 64-bit integers (for atomic min/max)
   unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -66,17 +70,15 @@ struct Counters {
   int n_term;
   int n_merge;
   int n_ovf;
-  int n_pairs;
   int pair_overflow;
   int n_min;
   int nonfinite;
-  int n_cand;
   int cand_overflow;
-  int n_pend;
-  int pad0;
-  long long cache_hits;
-  long long cache_inserts;
-  long long cache_fail;
+  // append counters are 64-bit: a round can propose more than 2^31 candidates,
+  // and an index is only ever used after a 64-bit check against its capacity
+  long long n_pairs;
+  long long n_cand;
+  long long n_pend;
   unsigned long long bb_lo[2];
   unsigned long long bb_hi[2];
   long long cluster_evals;
@@ -84,6 +86,9 @@ struct Counters {
   long long n_tiles;
   long long n_chunks;
   long long visits[4];  // per timed search kernel
+  long long cache_hits;
+  long long cache_inserts;
+  long long cache_fail;
 };
 
 // All device arrays of one clustering call. Slots are storage indices of
@@ -108,7 +113,8 @@ struct State {
   double *wcen;    // d centroid coordinates per slot (wsum / csize)
   float *lo, *hi;  // d-dimensional bounding box per slot (complete, average)
   int *ext;        // complete: 2d original point indices attaining the box faces (lo_k, hi_k)
-  double *crad;    // complete: upper bound of the largest centroid-to-point distance
+  double *crad;    // complete, average: upper bound of the largest centroid-to-point distance
+  double *cvar;    // complete, average: sum of squared deviations from the centroid (FP64)
   int *sup;        // complete, d == 2: kSupDirs original point indices, the cluster's
                    // support point in direction (cos, sin)(2 pi k / kSupDirs)
   const float *xin;  // the caller's points (original order)
@@ -172,6 +178,7 @@ struct State {
   unsigned long long *gmin, *gmax;  // per-dimension ordered bits of the centroid range
   double *gscale;       // 1 value
   int *term_pos;        // active-list index of each terminal
+  int tb0, tb1;         // terminals [tb0, tb1) of the current Gram batch
   double *tile_v;
   long long pair_cap, tile_cap;
   int cell_cap;
@@ -199,6 +206,7 @@ void launch_init(State &S, const float *x, hipStream_t s);
 void launch_round(State &S, int round, int nact_host, hipStream_t s, bool &need_pairs);
 void launch_emit_fallback(State &S, int nact_host, hipStream_t s);
 void launch_gram_keys(State &S, hipStream_t s);
+void launch_gram_batch(State &S, int nact_host, hipStream_t s);
 void launch_cache_clear(State &S, unsigned long long *keys, unsigned long long *vals,
                         unsigned long long mask, hipStream_t s);
 void launch_cache_rebuild(State &S, const unsigned long long *okeys, const unsigned long long *ovals,

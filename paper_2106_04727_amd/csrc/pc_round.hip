@@ -114,6 +114,17 @@ __global__ void k_reset_round(Counters *c) {
   c->n_tiles = 0;
 }
 
+// per Gram batch: the append counters start empty
+__global__ void k_reset_batch(Counters *c) {
+  c->n_cand = 0;
+  c->n_pairs = 0;
+  c->n_pend = 0;
+  c->cand_overflow = 0;
+  c->pair_overflow = 0;
+  c->n_tiles = 0;
+  c->n_chunks = 0;
+}
+
 __global__ void k_check_finite(const float *x, long long count, Counters *c) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
        i += (long long)gridDim.x * blockDim.x)
@@ -188,7 +199,10 @@ __global__ void k_init_slots(State S, const float *x, const unsigned *perm) {
     S.wsum[(size_t)s * d + k] = (double)v;
     S.wcen[(size_t)s * d + k] = (double)v;
   }
-  if (S.linkage != kWard) S.crad[s] = 0.0;
+  if (S.linkage != kWard) {
+    S.crad[s] = 0.0;
+    S.cvar[s] = 0.0;
+  }
   if (S.linkage == kComplete) {
     if (d == 2)
       for (int k = 0; k < kSupDirs; ++k) S.sup[(size_t)s * kSupDirs + k] = p;
@@ -779,7 +793,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                 }
                 if (PASS == 0 && cost > kInlinePairs) {
                   // remember it: the final bound decides later whether it is evaluated
-                  const int ci = atomicAdd(&S.cnt->n_cand, 1);
+                  const long long ci = append_slot(&S.cnt->n_cand);
                   if (ci < S.cand_cap) {
                     S.cd_t[ci] = ti;
                     S.cd_c[ci] = s;
@@ -816,7 +830,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                     double v;
                     if (cache_find(S, pair_key(S.node[t], S.node[s]), v) == 1) continue;  // counted in pass 0
                   }
-                  const int p = atomicAdd(&S.cnt->n_pairs, 1);
+                  const long long p = append_slot(&S.cnt->n_pairs);
                   if (p < S.pair_cap) {
                     S.pr_t[p] = ti;
                     S.pr_c[p] = s;
@@ -868,7 +882,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
 template <int LINK>
 __global__ void k_cand_emit(State S, const int *t_ovf) {
   if (S.cnt->cand_overflow) return;
-  const int nc = S.cnt->n_cand;
+  const int nc = (int)min(S.cnt->n_cand, S.cand_cap);
   const int d = S.d;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
     const int ti = S.cd_t[i];
@@ -885,7 +899,7 @@ __global__ void k_cand_emit(State S, const int *t_ovf) {
       // claim the pair; if another terminal already did, wait for its value
       const int r = cache_claim(S, pair_key(S.node[S.term[ti]], S.node[c]));
       if (r == 2) {
-        const int q = atomicAdd(&S.cnt->n_pend, 1);
+        const long long q = append_slot(&S.cnt->n_pend);
         if (q < S.pair_cap) {
           S.pd_t[q] = ti;
           S.pd_c[q] = c;
@@ -895,7 +909,7 @@ __global__ void k_cand_emit(State S, const int *t_ovf) {
         continue;
       }
     }
-    const int p = atomicAdd(&S.cnt->n_pairs, 1);
+    const long long p = append_slot(&S.cnt->n_pairs);
     if (p < S.pair_cap) {
       S.pr_t[p] = ti;
       S.pr_c[p] = c;
@@ -1066,7 +1080,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
                   double v;
                   if (cache_find(S, pair_key(S.node[t], S.node[sl]), v) == 1) continue;  // counted in pass 0
                 }
-                const int pp = atomicAdd(&S.cnt->n_pairs, 1);
+                const long long pp = append_slot(&S.cnt->n_pairs);
                 if (pp < S.pair_cap) {
                   S.pr_t[pp] = ti;
                   S.pr_c[pp] = sl;
@@ -1304,7 +1318,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
             if (lb > beta * kSlack) continue;
           }
         }
-        const int p = atomicAdd(&S.cnt->n_pairs, 1);
+        const long long p = append_slot(&S.cnt->n_pairs);
         if (p < S.pair_cap) {
           S.pr_t[p] = ti;
           S.pr_c[p] = s;
@@ -1335,7 +1349,7 @@ __device__ __forceinline__ void pair_orient(const State &S, int p, int &begR, in
 }
 
 __global__ void k_pair_tiles(State S, long long *ntl) {
-  const int np = S.cnt->n_pairs;
+  const int np = (int)min(S.cnt->n_pairs, S.pair_cap);
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
     int br, nr, bs, ns;
     pair_orient(S, p, br, nr, bs, ns);
@@ -1353,7 +1367,7 @@ __global__ __launch_bounds__(kBlock) void k_tiles_avg(State S, long long ntiles)
   constexpr int kW = kBlock / kWave;
   constexpr int MD = MAXD > 0 ? MAXD : 1;
   __shared__ double rows[kW][kTile][MD];
-  const int np = S.cnt->n_pairs;
+  const int np = (int)min(S.cnt->n_pairs, S.pair_cap);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int d = S.d;
   long long ppairs = 0;
@@ -1436,7 +1450,7 @@ __device__ __forceinline__ void pair_slots(const State &S, int p, int &r, int &q
 }
 
 __global__ void k_pair_prep_comp(State S, long long *nch) {
-  const int np = S.cnt->n_pairs;
+  const int np = (int)min(S.cnt->n_pairs, S.pair_cap);
   const int d = S.d;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
     int r, q;
@@ -1478,7 +1492,7 @@ __device__ __forceinline__ double point_far_ub(const float *x, const State &S, i
 __global__ __launch_bounds__(kBlock) void k_filter_comp(State S, long long nchunks) {
   __shared__ int sp;
   __shared__ double vtx[2][kSupDirs][2];  // enclosing polygons of R (0) and S (1), d == 2
-  const int np = S.cnt->n_pairs;
+  const int np = (int)min(S.cnt->n_pairs, S.pair_cap);
   const int d = S.d;
   for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
     if (threadIdx.x == 0) {
@@ -1533,7 +1547,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_comp(State S, long long nchun
 }
 
 __global__ void k_pair_tiles_f(State S, long long *ntl) {
-  const int np = S.cnt->n_pairs;
+  const int np = (int)min(S.cnt->n_pairs, S.pair_cap);
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
     const int kr = S.pr_kR[p], ks = S.pr_kS[p];
     ntl[p] = (long long)((kr + kTile - 1) / kTile) * (long long)((ks + kTile - 1) / kTile);
@@ -1549,7 +1563,7 @@ __global__ __launch_bounds__(kBlock) void k_tiles_comp(State S) {
   constexpr int kW = kBlock / kWave;
   constexpr int MD = MAXD > 0 ? MAXD : 1;
   __shared__ double rows[kW][kTile][MD];
-  const int np = S.cnt->n_pairs;
+  const int np = (int)min(S.cnt->n_pairs, S.pair_cap);
   const long long ntiles = S.cnt->n_tiles;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int d = S.d;
@@ -1626,7 +1640,7 @@ __global__ __launch_bounds__(kBlock) void k_tiles_comp(State S) {
 
 // Per pair: finish the value, then WriteMin into its terminal's best value.
 __global__ __launch_bounds__(kBlock) void k_pair_finish(State S, int link) {
-  const int np = S.cnt->n_pairs;
+  const int np = (int)min(S.cnt->n_pairs, S.pair_cap);
   const int lane = threadIdx.x & (kWave - 1);
   const int wave0 = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int nwaves = (gridDim.x * blockDim.x) / kWave;
@@ -1655,13 +1669,13 @@ __global__ __launch_bounds__(kBlock) void k_pair_finish(State S, int link) {
 }
 
 __global__ void k_term_key_reset(State S) {
-  const int nterm = S.cnt->n_term;
-  for (int ti = blockIdx.x * blockDim.x + threadIdx.x; ti < nterm; ti += gridDim.x * blockDim.x)
+  const int nterm = min(S.tb1, S.cnt->n_term);
+  for (int ti = S.tb0 + blockIdx.x * blockDim.x + threadIdx.x; ti < nterm; ti += gridDim.x * blockDim.x)
     if (pos_bits(S.t_best[ti]) != S.t_min[ti]) S.t_key[ti] = kNoKey;
 }
 
 __global__ void k_pair_key(State S) {
-  const int np = S.cnt->n_pairs;
+  const int np = (int)min(S.cnt->n_pairs, S.pair_cap);
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
     const int ti = S.pr_t[p];
     if (pos_bits(S.pr_v[p]) == S.t_min[ti]) {
@@ -1673,7 +1687,7 @@ __global__ void k_pair_key(State S) {
 
 // Pairs another terminal evaluated this round: take the stored value.
 __global__ void k_pending_min(State S) {
-  const int np = S.cnt->n_pend;
+  const int np = (int)min(S.cnt->n_pend, S.pair_cap);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
     const int ti = S.pd_t[i], c = S.pd_c[i];
     double v;
@@ -1686,7 +1700,7 @@ __global__ void k_pending_min(State S) {
 }
 
 __global__ void k_pending_key(State S) {
-  const int np = S.cnt->n_pend;
+  const int np = (int)min(S.cnt->n_pend, S.pair_cap);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
     const int ti = S.pd_t[i], c = S.pd_c[i];
     double v;
@@ -1798,8 +1812,8 @@ __global__ void k_term_pos(State S) {
 
 template <int LINK>
 __global__ void k_gram_init(State S, int *t_ovf) {
-  const int nterm = S.cnt->n_term;
-  for (int ti = blockIdx.x * blockDim.x + threadIdx.x; ti < nterm; ti += gridDim.x * blockDim.x) {
+  const int nterm = min(S.tb1, S.cnt->n_term);
+  for (int ti = S.tb0 + blockIdx.x * blockDim.x + threadIdx.x; ti < nterm; ti += gridDim.x * blockDim.x) {
     S.t_best[ti] = INFINITY;
     S.t_key[ti] = kNoKey;
     S.t_min[ti] = pos_bits(INFINITY);
@@ -1823,21 +1837,32 @@ __device__ __forceinline__ void gram_bounds(double d2h, double nq, double nc, in
   hi2 = dm + e;
 }
 
+// Key bounds of a pair from its centroid-distance bounds lo2 <= |cq-cc|^2 <= hi2
+// (scaled units), radius bounds r and mean squared spreads v = Var/size:
+//   Ward      key = w |cq - cc|^2 (Table 1)
+//   complete  mean of |x-y|^2 over pairs = |cq-cc|^2 + vq + vc <= key
+//             key <= (|cq - cc| + rq + rc)^2
+//   average   |cq - cc| <= key (Sec. 4.2) and, by Jensen, key <= sqrt(mean
+//             of |x-y|^2 over pairs) = sqrt(|cq-cc|^2 + vq + vc)
 template <int LINK>
 __device__ __forceinline__ void gram_keys(double lo2, double hi2, double sc, int nq, int nc, double rq, double rc,
-                                          double &klo, double &khi) {
+                                          double vq, double vc, double &klo, double &khi) {
   const double is2 = 1.0 / (sc * sc);
   if (LINK == kWard) {
     const double w = (2.0 * (double)nq * (double)nc) / ((double)nq + (double)nc);
     klo = w * lo2 * is2 * (1.0 - 1e-12);
     khi = w * hi2 * is2 * (1.0 + 1e-12);
   } else if (LINK == kComplete) {
-    klo = lo2 * is2 * (1.0 - 1e-12);
+    // the spreads come from FP64 merge updates: relative and absolute margins
+    const double vlo = (vq + vc) * (1.0 - 1e-6) - 1e-12 * is2;
+    klo = (lo2 * is2 + (vlo > 0.0 ? vlo : 0.0)) * (1.0 - 1e-12);
     const double u = sqrt(hi2 * is2) + rq + rc;
     khi = u * u * (1.0 + 1e-12);
   } else {
     klo = sqrt(lo2 * is2) * (1.0 - 1e-12);
-    khi = (sqrt(hi2 * is2) + rq + rc) * (1.0 + 1e-12);
+    const double u1 = sqrt(hi2 * is2) + rq + rc;
+    const double u2 = sqrt(hi2 * is2 + (vq + vc) * (1.0 + 1e-6) + 1e-12 * is2);
+    khi = (u1 < u2 ? u1 : u2) * (1.0 + 1e-12);
   }
 }
 
@@ -1845,11 +1870,11 @@ template <int LINK, int KP, int PASS>
 __global__ __launch_bounds__(kBlock) void k_gram(State S) {
   __shared__ __attribute__((aligned(16))) _Float16 sq[kGT][KP];
   __shared__ __attribute__((aligned(16))) _Float16 sc[kGT][KP];
-  __shared__ double qn[kGT], cn[kGT], qr[kGT], cr[kGT], qb[kGT];
+  __shared__ double qn[kGT], cn[kGT], qr[kGT], cr[kGT], qb[kGT], qv[kGT], cv2[kGT];
   __shared__ int qs[kGT], cs[kGT], qz[kGT], cz[kGT], qt[kGT];
   __shared__ double rmin[4][32];
-  const int nterm = S.cnt->n_term, nact = S.cnt->n_act;
-  const int q0 = blockIdx.x * kGT;
+  const int nterm = min(S.tb1, S.cnt->n_term), nact = S.cnt->n_act;  // this batch: [tb0, nterm)
+  const int q0 = S.tb0 + blockIdx.x * kGT;
   if (q0 >= nterm) return;  // uniform per block
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
@@ -1872,6 +1897,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
       qn[r] = S.gnorm[pi];
       qz[r] = S.csize[t];
       qr[r] = LINK != kWard ? S.crad[t] : 0.0;
+      qv[r] = LINK != kWard ? S.cvar[t] / (double)S.csize[t] : 0.0;
       qb[r] = PASS == 1 ? S.t_beta[ti] * kSlack : 0.0;
     } else {
       qs[r] = -1;
@@ -1898,6 +1924,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
         cn[r] = S.gnorm[ci];
         cz[r] = S.csize[sl];
         cr[r] = LINK != kWard ? S.crad[sl] : 0.0;
+        cv2[r] = LINK != kWard ? S.cvar[sl] / (double)S.csize[sl] : 0.0;
       } else {
         cs[r] = -2;
       }
@@ -1920,12 +1947,12 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
       const double d2h = qn[row] + cn[col] - 2.0 * (double)acc[i];
       double lo2, hi2, klo, khi;
       gram_bounds(d2h, qn[row], cn[col], d, KP, lo2, hi2);
-      gram_keys<LINK>(lo2, hi2, scale, qz[row], cz[col], qr[row], cr[col], klo, khi);
+      gram_keys<LINK>(lo2, hi2, scale, qz[row], cz[col], qr[row], cr[col], qv[row], cv2[col], klo, khi);
       ++pairs;
       if (PASS == 0) {
         run[i] = khi < run[i] ? khi : run[i];
       } else if (klo <= qb[row]) {
-        const int k = atomicAdd(&S.cnt->n_cand, 1);
+        const long long k = append_slot(&S.cnt->n_cand);
         if (k < S.cand_cap) {
           S.cd_t[k] = qt[row];
           S.cd_c[k] = cslot;
@@ -1967,7 +1994,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
 template <int LINK>
 __global__ void k_gram_exact(State S) {
   if (S.cnt->cand_overflow) return;  // the round is redone with a larger record
-  const int nc = S.cnt->n_cand, d = S.d;
+  const int nc = (int)min(S.cnt->n_cand, S.cand_cap), d = S.d;
   long long evals = 0, ppairs = 0, hits = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
     const int ti = S.cd_t[i], c = S.cd_c[i];
@@ -1992,7 +2019,7 @@ __global__ void k_gram_exact(State S) {
           ++hits;
         } else {
           if (S.cache_mask && cache_claim(S, pk) == 2) {
-            const int q = atomicAdd(&S.cnt->n_pend, 1);
+            const long long q = append_slot(&S.cnt->n_pend);
             if (q < S.pair_cap) {
               S.pd_t[q] = ti;
               S.pd_c[q] = c;
@@ -2001,7 +2028,7 @@ __global__ void k_gram_exact(State S) {
             }
             continue;
           }
-          const int p = atomicAdd(&S.cnt->n_pairs, 1);
+          const long long p = append_slot(&S.cnt->n_pairs);
           if (p < S.pair_cap) {
             S.pr_t[p] = ti;
             S.pr_c[p] = c;
@@ -2025,7 +2052,7 @@ __global__ void k_gram_exact(State S) {
 // recorded candidates that reach it.
 __global__ void k_gram_key(State S) {
   if (S.cnt->cand_overflow) return;
-  const int nc = S.cnt->n_cand;
+  const int nc = (int)min(S.cnt->n_cand, S.cand_cap);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
     const double v = S.cd_v[i];
     if (!(v >= 0.0)) continue;
@@ -2127,6 +2154,14 @@ __global__ void k_merge(State S, int base) {
       }
       const double ra = sqrt(da) + S.crad[a], rb = sqrt(db) + S.crad[b];
       S.crad[a] = (ra > rb ? ra : rb) * (1.0 + 1e-12);
+      // Var(A u B) = Var(A) + Var(B) + |A||B|/(|A|+|B|) |cA - cB|^2 (sums of
+      // squared deviations; the merge rule of Sec. 2.1 with its size factor)
+      double cab = 0.0;
+      for (int k = 0; k < d; ++k) {
+        const double t = S.wcen[(size_t)a * d + k] - S.wcen[(size_t)b * d + k];
+        cab += t * t;
+      }
+      S.cvar[a] = S.cvar[a] + S.cvar[b] + ((double)sa * (double)sb / (double)ns) * cab;
     }
     if (S.linkage == kComplete) {
       if (d <= kExtMaxDim)
@@ -2315,8 +2350,9 @@ void launch_emit(State &S, int nact, hipStream_t s, int *t_ovf) {
 
 template <int LINK, int KP>
 void launch_gram_kp(State &S, int nact, hipStream_t s) {
-  const int gx = (nact + kGT - 1) / kGT;
-  int gy = 4096 / gx;
+  const int nb = S.tb1 - S.tb0;
+  const int gx = (nb + kGT - 1) / kGT;
+  int gy = 4096 / (gx > 0 ? gx : 1);
   const int maxy = (nact + kGT - 1) / kGT;
   gy = gy < 1 ? 1 : (gy > maxy ? maxy : gy);
   tmark(S, 0, false, s);
@@ -2328,14 +2364,18 @@ void launch_gram_kp(State &S, int nact, hipStream_t s) {
   tmark(S, 3, true, s);
 }
 
-template <int LINK>
-void launch_gram(State &S, int nact, hipStream_t s, int *t_ovf) {
-  const int gb = nblk(nact, 2048);
+// once per round: FP16 centroids (the terminals are batched afterwards)
+void launch_gram_setup(State &S, int nact, hipStream_t s) {
   k_gram_reset<<<1, kGramMaxDim, 0, s>>>(S);
   k_gram_range<<<nblk((long long)nact * kWave, 1024), kBlock, 0, s>>>(S);
   k_gram_setup<<<1, kGramMaxDim, 0, s>>>(S);
   k_gram_prep<<<nblk((long long)nact * kWave, 4096), kBlock, 0, s>>>(S);
-  k_gram_init<LINK><<<gb, kBlock, 0, s>>>(S, t_ovf);
+}
+
+template <int LINK>
+void launch_gram_batch_t(State &S, int nact, hipStream_t s) {
+  k_reset_batch<<<1, 1, 0, s>>>(S.cnt);
+  k_gram_init<LINK><<<nblk(S.tb1 - S.tb0, 2048), kBlock, 0, s>>>(S, S.cell_rank);
   switch (S.gkp) {
   case 16: launch_gram_kp<LINK, 16>(S, nact, s); break;
   case 32: launch_gram_kp<LINK, 32>(S, nact, s); break;
@@ -2347,6 +2387,14 @@ void launch_gram(State &S, int nact, hipStream_t s, int *t_ovf) {
 }  // namespace
 
 void launch_gram_keys(State &S, hipStream_t s) { k_gram_key<<<2048, kBlock, 0, s>>>(S); }
+
+void launch_gram_batch(State &S, int nact, hipStream_t s) {
+  switch (S.linkage) {
+  case kWard: launch_gram_batch_t<kWard>(S, nact, s); break;
+  case kComplete: launch_gram_batch_t<kComplete>(S, nact, s); break;
+  default: launch_gram_batch_t<kAverage>(S, nact, s); break;
+  }
+}
 
 void launch_cache_clear(State &S, unsigned long long *keys, unsigned long long *vals, unsigned long long mask,
                         hipStream_t s) {
@@ -2407,12 +2455,10 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
   int *t_ovf = S.cell_rank;  // per-terminal hand-off flags (cell ranks are no longer needed)
   need_pairs = false;
   if (S.gram) {
+    // the host then runs the terminals in batches (launch_gram_batch)
     k_term_pos<<<gb, kBlock, 0, s>>>(S);
-    switch (S.linkage) {
-    case kWard: launch_gram<kWard>(S, nact, s, t_ovf); break;
-    case kComplete: launch_gram<kComplete>(S, nact, s, t_ovf); need_pairs = true; break;
-    default: launch_gram<kAverage>(S, nact, s, t_ovf); need_pairs = true; break;
-    }
+    launch_gram_setup(S, nact, s);
+    need_pairs = S.linkage != kWard;
     return;
   }
   switch (S.linkage) {
@@ -2449,10 +2495,10 @@ void launch_pairs_prefix(State &S, int npairs, hipStream_t s) {
   long long *tmp = S.pr_tile0;  // per-pair counts, then their exclusive prefix (in place)
   if (S.linkage == kComplete) {
     k_pair_prep_comp<<<nblk(npairs, 2048), kBlock, 0, s>>>(S, S.pr_cbase);
-    scan_exclusive_i64(S.pr_cbase, S.pr_cbase, npairs, &S.cnt->n_pairs, &S.cnt->n_chunks, S.part, s);
+    scan_exclusive_i64(S.pr_cbase, S.pr_cbase, npairs, nullptr, &S.cnt->n_chunks, S.part, s);
   } else {
     k_pair_tiles<<<nblk(npairs, 2048), kBlock, 0, s>>>(S, tmp);
-    scan_exclusive_i64(tmp, S.pr_tile0, npairs, &S.cnt->n_pairs, &S.cnt->n_tiles, S.part, s);
+    scan_exclusive_i64(tmp, S.pr_tile0, npairs, nullptr, &S.cnt->n_tiles, S.part, s);
   }
 }
 
@@ -2463,7 +2509,7 @@ void launch_pairs(State &S, int round, int npairs, long long work, hipStream_t s
     if (S.linkage == kComplete) {
       k_filter_comp<<<(int)std::min<long long>(work, 1 << 20), kBlock, 0, s>>>(S, work);
       k_pair_tiles_f<<<nblk(npairs, 2048), kBlock, 0, s>>>(S, S.pr_tile0);
-      scan_exclusive_i64(S.pr_tile0, S.pr_tile0, npairs, &S.cnt->n_pairs, &S.cnt->n_tiles, S.part, s);
+      scan_exclusive_i64(S.pr_tile0, S.pr_tile0, npairs, nullptr, &S.cnt->n_tiles, S.part, s);
       tmark(S, 2, false, s);
       if (S.d <= 2) k_tiles_comp<2><<<2048, kBlock, 0, s>>>(S);
       else if (S.d <= 4) k_tiles_comp<4><<<2048, kBlock, 0, s>>>(S);

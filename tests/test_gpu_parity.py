@@ -205,3 +205,18 @@ def test_gram_record_overflow(pc, link, monkeypatch):
     monkeypatch.setenv("PC_TEST_CAND_CAP", "64")
     Z1 = pc.hac(x, link)
     assert np.array_equal(Z0, Z1)
+
+
+@pytest.mark.parametrize("link", LINKS)
+def test_gram_batches(pc, link, monkeypatch):
+    """The Gram search takes terminals in batches (each with its own bounded
+    candidate record and pair list); the batch size must not change the rows."""
+    x = synth.sphere_blobs(2500, 64, 30, 0.1, 52)
+    Z0 = pc.hac(x, link)
+    monkeypatch.setenv("PC_TEST_GRAM_BATCH", "37")
+    Z1 = pc.hac(x, link)
+    monkeypatch.setenv("PC_TEST_CAND_CAP", "256")
+    Z2 = pc.hac(x, link)
+    assert np.array_equal(Z0, Z1) and np.array_equal(Z0, Z2)
+    Zo, _ = oracle.nnchain(x, link, threads=8)
+    assert _trees.same_tree(Z0, Zo, 2500, rtol=RTOL[link])

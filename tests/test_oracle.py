@@ -231,3 +231,29 @@ def test_thread_count_does_not_change_result():
         Z1, _ = oracle.nnchain(x, link, threads=1)
         Z8, _ = oracle.nnchain(x, link, threads=8)
         assert np.array_equal(Z1, Z8)
+
+
+def test_spread_identities_used_by_bounds():
+    """Table 1's avg-2 row: mean over pairs of |x-y|^2 equals
+    |cA-cB|^2 + Var(A)/|A| + Var(B)/|B| (Var = sum of squared deviations);
+    and Var(A u B) = Var(A) + Var(B) + |A||B|/(|A|+|B|) |cA-cB|^2 (the merge
+    rule of Sec. 2.1 read with its size factor). Complete linkage is at least
+    the root of the first quantity, average linkage at most (Jensen)."""
+    rng = np.random.default_rng(17)
+    x = rng.normal(size=(400, 7)).astype(np.float32)
+    for _ in range(30):
+        p = rng.permutation(400)
+        a, b = rng.integers(1, 60, 2)
+        A, B = x[p[:a]].astype(np.float64), x[p[a : a + b]].astype(np.float64)
+        D2 = ((A[:, None] - B[None]) ** 2).sum(-1)
+        ca, cb = A.mean(0), B.mean(0)
+        va, vb = ((A - ca) ** 2).sum(), ((B - cb) ** 2).sum()
+        closed = ((ca - cb) ** 2).sum() + va / a + vb / b
+        assert D2.mean() == pytest.approx(closed, rel=1e-12)
+        U = np.vstack([A, B])
+        vu = ((U - U.mean(0)) ** 2).sum()
+        assert vu == pytest.approx(va + vb + a * b / (a + b) * ((ca - cb) ** 2).sum(), rel=1e-12)
+        comp = oracle.linkage_dist(x, "complete", p[:a], p[a : a + b])
+        avg = oracle.linkage_dist(x, "average", p[:a], p[a : a + b])
+        assert comp * comp >= closed * (1 - 1e-12)
+        assert avg <= np.sqrt(closed) * (1 + 1e-12)
