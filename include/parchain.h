@@ -102,6 +102,8 @@ typedef struct {
     int64_t cache_hits;       /* pair distances reused from the cache */
     int64_t cache_inserts;    /* cache slots taken (claims and stores) */
     int64_t cache_fail;       /* stores dropped because the probe window was full */
+    int64_t cache_derived;    /* pair values combined from cached parts
+                                 (Lance-Williams rules, Table 2 / Sec. 5) */
 } pc_stats;
 
 typedef struct pc_context pc_context;

@@ -54,6 +54,7 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   S.csize = c.take<int>(n);
   S.node = c.take<int>(n);
   S.node2slot = c.take<int>(2 * n);
+  S.nparent = c.take<int>(pts ? 2 * n : 1);
   S.succ = c.take<int>(n);
   S.succ_node = c.take<int>(n);
   S.predd = c.take<unsigned>(n);
@@ -94,10 +95,10 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   S.item_lo = c.take<float>(grid && pts ? n * d : 1);
   S.item_hi = c.take<float>(grid && pts ? n * d : 1);
   const bool gram = d >= kGramMinDim && d <= kGramMaxDim;
-  const int kp = d <= 16 ? 16 : (d <= 32 ? 32 : (d <= 64 ? 64 : 128));
+  const int kp = gram_kp(d);
   S.gkp = kp;
   S.g16 = c.take<_Float16>(gram ? n * kp : 1);
-  S.gnorm = c.take<double>(gram ? n : 1);
+  S.gq = c.take<float4>(gram ? n : 1);
   S.gorg = c.take<double>(gram ? d : 1);
   S.gmin = c.take<unsigned long long>(gram ? d : 1);
   S.gmax = c.take<unsigned long long>(gram ? d : 1);
@@ -247,9 +248,9 @@ static pc_status grow_part(pc_context *ctx, State &S, long long longest_scan) {
 
 static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
   if (cap > kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round needs more than 2^30 cluster pairs");
-  // per pair: tile prefix (i64), chunk prefix (i64), value (f64), t, c, kR, kS,
-  // pending t, pending c (i32)
-  const size_t per = 3 * sizeof(long long) + 6 * sizeof(int);
+  // per pair: tile prefix (i64), chunk prefix (i64), value (f64), pending
+  // value (f64), t, c, kR, kS, pending t, pending c (i32)
+  const size_t per = 4 * sizeof(long long) + 6 * sizeof(int);
   HIPCHK(grow(ctx->pairs, (size_t)cap * per + 1024));
   char *b = (char *)ctx->pairs.p;
   const long long pc = (long long)((ctx->pairs.bytes - 1024) / per);
@@ -257,7 +258,8 @@ static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
   S.pr_tile0 = (long long *)b;
   S.pr_cbase = S.pr_tile0 + pc;
   S.pr_v = (double *)(S.pr_cbase + pc);
-  S.pr_t = (int *)(S.pr_v + pc);
+  S.pd_v = S.pr_v + pc;
+  S.pr_t = (int *)(S.pd_v + pc);
   S.pr_c = S.pr_t + pc;
   S.pr_kR = S.pr_c + pc;
   S.pr_kS = S.pr_kR + pc;
@@ -442,12 +444,18 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     launch_round(S, (int)rounds, nact, s, need_pairs);
     HIPCHK(hipGetLastError());
     // evaluate the emitted pairs of the current terminals (tiles), then their keys
-    auto pairs_pipeline = [&](int np) -> pc_status {
+    // (too_big: the work exceeds the record limits; nothing was evaluated)
+    auto pairs_pipeline = [&](int np, bool &too_big) -> pc_status {
+      too_big = false;
       launch_pairs_prefix(S, np, s);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       long long work = 0;
+      if (np > 0 && (linkage == kComplete ? h.n_chunks * kChunk > 8 * kMaxRecord : h.n_tiles > 4 * kMaxRecord)) {
+        too_big = true;
+        return PC_OK;
+      }
       if (linkage == kComplete) {
         work = np > 0 ? h.n_chunks : 0;
         if (work * kChunk > S.fidx_cap) {
@@ -521,8 +529,18 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
         if (linkage == kWard) {
           launch_gram_keys(S, s);
         } else {
-          pc_status st = pairs_pipeline((int)h.n_pairs);
+          bool too_big = false;
+          pc_status st = pairs_pipeline((int)h.n_pairs, too_big);
           if (st != PC_OK) return st;
+          if (too_big) {
+            // fewer terminals per batch; the claims of this batch are dropped
+            S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;
+            launch_cache_unclaim(S, s);
+            if (t1 - t0 <= 1) return fail(PC_ERR_OUT_OF_MEMORY, "one terminal's pair evaluation exceeds the limits");
+            tb = std::max<long long>(1, (t1 - t0) / 4);
+            gram_batch = tb;
+            continue;
+          }
         }
         t0 = t1;
       }
@@ -559,8 +577,10 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
         }
         if (h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap) return fail(PC_ERR_DEVICE, "pair list overflow");
       }
-      pc_status st = pairs_pipeline((int)h.n_pairs);
+      bool too_big = false;
+      pc_status st = pairs_pipeline((int)h.n_pairs, too_big);
       if (st != PC_OK) return st;
+      if (too_big) return fail(PC_ERR_OUT_OF_MEMORY, "a round's pair evaluation exceeds the record limits");
     }
     launch_round_tail(S, (int)rounds, nact, merges, s);
     HIPCHK(hipGetLastError());
@@ -582,6 +602,9 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
       cache_cur = nxt;
     }
     take_times();
+    if (debug)
+      fprintf(stderr, "[parchain] round %lld done: nact %d nterm %d merged %d evals %lld pp %lld cand %lld\n", rounds,
+              nact, h.n_term, h.n_merge, h.cluster_evals, h.point_pairs, h.n_cand);
     if (h.n_merge <= 0) return fail(PC_ERR_DEVICE, "round merged nothing");
     terms += h.n_term;
     ovfq += h.n_ovf;
@@ -621,6 +644,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     stats->cache_hits = h.cache_hits;
     stats->cache_inserts = h.cache_inserts;
     stats->cache_fail = h.cache_fail;
+    stats->cache_derived = h.cache_derived;
   }
   g_err.clear();
   return PC_OK;

@@ -21,6 +21,16 @@ constexpr int kExtMaxDim = 4;      // extreme-point bounds kept up to this d
 constexpr int kSupDirs = 64;       // d == 2, complete: support points in 64 fixed directions
 constexpr int kGramMinDim = 4;     // Gram (MFMA) search from this d on
 constexpr int kGramMaxDim = 128;   // largest d of the Gram search (K = 128 in LDS)
+// MFMA depth of the Gram tiles: the dimension plus two augmented
+// coordinates (the norm terms of the bound pass), in steps of 16
+inline int gram_kp(int d) {
+  if (d + 2 <= 16) return 16;
+  if (d + 2 <= 32) return 32;
+  if (d + 2 <= 64) return 64;
+  if (d + 2 <= 80) return 80;
+  if (d + 2 <= 128) return 128;
+  return 144;
+}
 constexpr uint32_t kInfBits = 0x7f800000u;
 
 enum Linkage { kComplete = 0, kAverage = 1, kWard = 2 };
@@ -89,6 +99,7 @@ struct Counters {
   long long cache_hits;
   long long cache_inserts;
   long long cache_fail;
+  long long cache_derived;
 };
 
 // All device arrays of one clustering call. Slots are storage indices of
@@ -162,7 +173,8 @@ struct State {
   unsigned long long *ck, *cv;
   unsigned long long cache_mask;
   int *node2slot;       // node id -> slot (valid while the node is alive)
-  int *pd_t, *pd_c;     // pairs whose value another terminal is computing this round
+  int *pd_t, *pd_c;     // pairs whose value another terminal is computing this round,
+  double *pd_v;         // or whose value was combined from cached parts (else -1)
   // large candidates recorded by the bound pass (terminal index, slot, lower bound)
   int *cd_t, *cd_c;
   double *cd_lb;
@@ -173,7 +185,8 @@ struct State {
   int gram;             // 1: this call searches with MFMA Gram tiles
   int gkp;              // padded K (multiple of 16)
   _Float16 *g16;        // n x gkp, in active-list order
-  double *gnorm;
+  float4 *gq;  // per active item: pass-0 norm term, rigorous norm, rounding error, size/spread term
+  int *nparent;  // node -> parent node (-1: none yet); kept when the cache is on
   double *gorg;         // d
   unsigned long long *gmin, *gmax;  // per-dimension ordered bits of the centroid range
   double *gscale;       // 1 value

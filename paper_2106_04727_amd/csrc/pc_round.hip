@@ -184,6 +184,10 @@ __global__ void k_init_slots(State S, const float *x, const unsigned *perm) {
   S.csize[s] = 1;
   S.node[s] = p;
   S.node2slot[p] = s;
+  if (S.cache_mask) {
+    S.nparent[s] = -1;
+    S.nparent[S.n + s] = -1;
+  }
   S.succ[s] = -1;
   S.succ_node[s] = -1;
   S.predd[s] = kInfBits;
@@ -494,7 +498,8 @@ __device__ int cache_claim(const State &S, unsigned long long key) {
   return 0;
 }
 
-__device__ void cache_fill(const State &S, unsigned long long key, double v) {
+// store a value (claimed slot or a new one); false if the probe window is full
+__device__ bool cache_fill(const State &S, unsigned long long key, double v) {
   const unsigned long long h = mix64(key);
   for (int i = 0; i < kCacheProbe; ++i) {
     const unsigned long long idx = (h + i) & S.cache_mask;
@@ -502,10 +507,84 @@ __device__ void cache_fill(const State &S, unsigned long long key, double v) {
     if (prev == kCacheEmpty || prev == key) {
       if (prev == kCacheEmpty) atomicAdd((unsigned long long *)&S.cnt->cache_inserts, 1ull);
       atomicExch(&S.cv[idx], pos_bits(v));
-      return;
+      return true;
     }
   }
   atomicAdd((unsigned long long *)&S.cnt->cache_fail, 1ull);
+  return false;
+}
+
+__device__ __forceinline__ int node_size(const State &S, int v) { return v < S.n ? 1 : S.row_size[v - S.n]; }
+
+// Value of the node pair (x, y) from the cache: stored directly, or combined
+// from the stored values of the parts of the newer node (its two children,
+// recursively up to DEPTH levels) by the Lance-Williams rules of Table 2 and
+// Sec. 5: complete takes the larger value (keys are monotone in the
+// distance), average the size-weighted mean (Eq. case 2; two levels give
+// Eq. case 1). A pair being evaluated this round (pending) is not combined.
+template <int DEPTH>
+__device__ bool cache_parts(const State &S, int x, int y, double &v) {
+  const int r = cache_find(S, pair_key(x, y), v);
+  if (r == 1) return true;
+  if constexpr (DEPTH == 0) {
+    return false;
+  } else {
+    if (r == 2) return false;
+    const int z = x > y ? x : y, o = x > y ? y : x;  // node ids grow with merge order
+    if (z < S.n) return false;
+    const int a = S.row_na[z - S.n], b = S.row_nb[z - S.n];
+    double va, vb;
+    if (!cache_parts<DEPTH - 1>(S, a, o, va) || !cache_parts<DEPTH - 1>(S, b, o, vb)) return false;
+    if (S.linkage == kComplete) {
+      v = va > vb ? va : vb;
+    } else {
+      const double sa = (double)node_size(S, a), sb = (double)node_size(S, b);
+      v = (sa * va + sb * vb) / (sa + sb);
+    }
+    return true;
+  }
+}
+
+// cache_parts with the children of the newer node as the first split; a
+// combined value is stored under (x, y) when `store` (then false if it could
+// not be stored). The grid search stores nothing while it runs: its emission
+// pass treats a stored value as one its bound pass already counted.
+__device__ bool cache_resolve(const State &S, int x, int y, double &v, bool store = true) {
+  if (!S.cache_mask) return false;
+  const int r = cache_find(S, pair_key(x, y), v);
+  if (r == 1) return true;
+  if (r == 2) return false;
+  const int z = x > y ? x : y, o = x > y ? y : x;
+  if (z < S.n) return false;
+  const int a = S.row_na[z - S.n], b = S.row_nb[z - S.n];
+  double va, vb;
+  if (!cache_parts<1>(S, a, o, va) || !cache_parts<1>(S, b, o, vb)) return false;
+  if (S.linkage == kComplete) {
+    v = va > vb ? va : vb;
+  } else {
+    const double sa = (double)node_size(S, a), sb = (double)node_size(S, b);
+    v = (sa * va + sb * vb) / (sa + sb);
+  }
+  if (store && !cache_fill(S, pair_key(x, y), v)) return false;
+  atomicAdd((unsigned long long *)&S.cnt->cache_derived, 1ull);
+  return true;
+}
+
+// A pair whose value combines from cached parts is not evaluated: it joins
+// the list of pairs whose values are read back from the cache.
+// Its value travels with the entry and is stored after the search.
+__device__ bool pend_if_resolved(const State &S, int ti, int c) {
+  double v;
+  if (!cache_resolve(S, S.node[S.term[ti]], S.node[c], v, false)) return false;
+  const long long q = append_slot(&S.cnt->n_pend);
+  if (q < S.pair_cap) {
+    S.pd_t[q] = ti;
+    S.pd_c[q] = c;
+    S.pd_v[q] = v;
+  } else {
+    S.cnt->pair_overflow = 1;
+  }
+  return true;
 }
 
 __global__ void k_cache_clear(unsigned long long *keys, unsigned long long *vals, unsigned long long mask) {
@@ -521,7 +600,19 @@ __device__ __forceinline__ bool node_alive(const State &S, int v) {
   return sl >= 0 && S.node[sl] == v;
 }
 
-// Move the live, valued entries of an old table into the (cleared) current one.
+// alive, or a child or grandchild of a live node: its entries can still be
+// combined into a live pair's value
+__device__ __forceinline__ bool node_recent(const State &S, int v) {
+  if (node_alive(S, v)) return true;
+  const int p = S.nparent[v];
+  if (p < 0) return false;
+  if (node_alive(S, p)) return true;
+  const int g = S.nparent[p];
+  return g >= 0 && node_alive(S, g);
+}
+
+// Move the valued entries of live pairs (and of their recent parts) of an old
+// table into the (cleared) current one.
 __global__ void k_cache_rebuild(State S, const unsigned long long *okeys, const unsigned long long *ovals,
                                 unsigned long long omask) {
   for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i <= omask;
@@ -529,7 +620,7 @@ __global__ void k_cache_rebuild(State S, const unsigned long long *okeys, const 
     const unsigned long long k = okeys[i], b = ovals[i];
     if (k == kCacheEmpty || b == kCachePending) continue;
     const int a = (int)(k >> 32), c = (int)(k & 0xffffffffu);
-    if (!node_alive(S, a) || !node_alive(S, c)) continue;
+    if (!node_recent(S, a) || !node_recent(S, c)) continue;
     cache_fill(S, k, pos_from_bits(b));
   }
 }
@@ -829,6 +920,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                   if (S.cache_mask) {
                     double v;
                     if (cache_find(S, pair_key(S.node[t], S.node[s]), v) == 1) continue;  // counted in pass 0
+                    if (pend_if_resolved(S, ti, s)) continue;
                   }
                   const long long p = append_slot(&S.cnt->n_pairs);
                   if (p < S.pair_cap) {
@@ -891,6 +983,7 @@ __global__ void k_cand_emit(State S, const int *t_ovf) {
     double lb = S.cd_lb[i];
     if (lb > beta * kSlack) continue;
     const int c = S.cd_c[i];
+    if (S.cache_mask && pend_if_resolved(S, ti, c)) continue;
     if (LINK == kComplete) {
       comp_lb_refine(S, S.term[ti], c, d, lb, beta * kSlack);
       if (lb > beta * kSlack) continue;
@@ -903,6 +996,7 @@ __global__ void k_cand_emit(State S, const int *t_ovf) {
         if (q < S.pair_cap) {
           S.pd_t[q] = ti;
           S.pd_c[q] = c;
+          S.pd_v[q] = -1.0;
         } else {
           S.cnt->pair_overflow = 1;
         }
@@ -1079,6 +1173,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
                 if (S.cache_mask) {
                   double v;
                   if (cache_find(S, pair_key(S.node[t], S.node[sl]), v) == 1) continue;  // counted in pass 0
+                  if (pend_if_resolved(S, ti, sl)) continue;
                 }
                 const long long pp = append_slot(&S.cnt->n_pairs);
                 if (pp < S.pair_cap) {
@@ -1318,6 +1413,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
             if (lb > beta * kSlack) continue;
           }
         }
+        if (S.cache_mask && pend_if_resolved(S, ti, s)) continue;
         const long long p = append_slot(&S.cnt->n_pairs);
         if (p < S.pair_cap) {
           S.pr_t[p] = ti;
@@ -1690,8 +1786,11 @@ __global__ void k_pending_min(State S) {
   const int np = (int)min(S.cnt->n_pend, S.pair_cap);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
     const int ti = S.pd_t[i], c = S.pd_c[i];
-    double v;
-    if (cache_find(S, pair_key(S.node[S.term[ti]], S.node[c]), v) != 1) {
+    double v = S.pd_v[i];
+    if (v >= 0.0) {
+      // combined from cached parts during the search: store it now
+      cache_fill(S, pair_key(S.node[S.term[ti]], S.node[c]), v);
+    } else if (cache_find(S, pair_key(S.node[S.term[ti]], S.node[c]), v) != 1) {
       S.cnt->nonfinite = 4;  // a claimed pair was not evaluated
       continue;
     }
@@ -1703,32 +1802,51 @@ __global__ void k_pending_key(State S) {
   const int np = (int)min(S.cnt->n_pend, S.pair_cap);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
     const int ti = S.pd_t[i], c = S.pd_c[i];
-    double v;
-    if (cache_find(S, pair_key(S.node[S.term[ti]], S.node[c]), v) == 1 && pos_bits(v) == S.t_min[ti])
-      atomicMin(&S.t_key[ti], make_key(S.cid[c], c));
+    double v = S.pd_v[i];
+    const bool have = v >= 0.0 || cache_find(S, pair_key(S.node[S.term[ti]], S.node[c]), v) == 1;
+    if (have && pos_bits(v) == S.t_min[ti]) atomicMin(&S.t_key[ti], make_key(S.cid[c], c));
   }
 }
 
 // ------------------------------------------------------------ Gram search --
 // For d >= kGramMinDim the centroid grid prunes poorly, so every terminal is
-// compared with every active cluster through MFMA Gram tiles, with exact FP64
-// refinement of every candidate the rounding bound cannot rule out:
+// compared with every active cluster through MFMA Gram tiles, and every
+// candidate that the rounding bounds cannot rule out is evaluated exactly in
+// FP64 afterwards:
 //   * centroids are recentred on the middle of their range, scaled into
-//     [-1, 1] and rounded to FP16; the norms are FP64 norms of the rounded
-//     vectors, so d2~ = |x~|^2 + |y~|^2 - 2 x~.y~ errs only by the rounding of
-//     the coordinates (which scales with the distance) and by the FP32
-//     accumulation inside the MFMA (gamma_K |x~||y~|);
-//   * pass 0: every terminal's smallest upper bound U on its key over all
-//     candidates (centroid distance plus radii bounds complete and average
-//     linkage; Table 1 for Ward);
-//   * pass 1: every candidate whose lower bound (the centroid distance bounds
-//     complete and average from below, Sec. 4.2-4.3) does not exceed U is
-//     recorded and evaluated exactly afterwards.
+//     [-1, 1] (distances scale by sc) and rounded to FP16 (x~);
+//   * per cluster the prep pass keeps |x~|^2, the FP64 norm eta of the
+//     rounding error x - x~ (rounded up) and an allowance e for the FP32
+//     accumulation of the dot products; with T = |x~ - y~| and D the scaled
+//     centroid distance, |D - T| <= eta_x + eta_y, and
+//     d2 = |x~|^2 + |y~|^2 - 2 x~.y~ is within e_x + e_y of T^2;
+//   * pass 0 (bound pass) picks, per terminal, the cluster with the smallest
+//     cheap key estimate (|x~-y~|^2 scaled by the Ward size factor, or plus
+//     the two spreads; the norm terms ride in two augmented coordinates, so
+//     the MFMA produces the estimate itself) and evaluates an FP64 upper bound
+//     of that cluster's key: exact for Ward (Table 1), exact for complete and
+//     average when the pair is cached or small, else the centroid-distance
+//     radius and spread bounds. Any upper bound of the nearest key will do;
+//   * pass 1 records every cluster whose rigorous lower bound (FP32 with
+//     outward margins) does not exceed that bound: Ward w D^2, complete
+//     D^2 + spreads (mean squared point distance <= largest), average D
+//     (centroid distance <= mean distance, Sec. 4.2).
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float float16v __attribute__((ext_vector_type(16)));
-constexpr int kGT = 64;                                    // block tile: 64 terminals x 64 candidates
-constexpr double kU16 = 1.0 / 2048.0 + 1.0 / 16777216.0;  // FP16 rounding (via FP32)
-constexpr double kEta16 = 1.0 / 33554432.0;                // half the FP16 subnormal spacing
+constexpr int kGT = 64;                      // block tile: 64 terminals x 64 candidates
+constexpr float kGMargin = 1.0f + 1.0f / 16384.0f;  // outward margin of the FP32 tests
+
+__device__ __forceinline__ float f32_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = nextafterf(f, INFINITY);
+  return f;
+}
+
+__device__ __forceinline__ float f32_dn(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = nextafterf(f, -INFINITY);
+  return f;
+}
 
 // per-dimension range of the active centroids: a wave per item, lanes over dims
 __global__ void k_gram_range(State S) {
@@ -1782,25 +1900,53 @@ __global__ void k_gram_reset(State S) {
   }
 }
 
-// FP16 copy of every active centroid (active-list order) and the FP64 norm of
-// the rounded vector: a wave per item, lanes over dims
+// FP16 copy of every active centroid (active-list order, zero beyond d) and
+// its FP32 terms: x = |x~|^2 (+ mean squared spread for complete/average:
+// the bound pass estimate), y = |x~|^2 - e rounded down, z = eta rounded up,
+// w = 1/size (Ward) or the mean squared spread rounded down (complete).
+// A wave per item, lanes over dims.
 __global__ void k_gram_prep(State S) {
   const int nact = S.cnt->n_act, d = S.d, kp = S.gkp;
   const double sc = *S.gscale;
   const int lane = threadIdx.x & (kWave - 1);
   const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, nw = (gridDim.x * blockDim.x) / kWave;
   for (int i = w0; i < nact; i += nw) {
-    const double *c = S.wcen + (size_t)S.act[i] * d;
-    double nrm = 0.0;
+    const int sl = S.act[i];
+    const double *c = S.wcen + (size_t)sl * d;
+    double nrm = 0.0, err = 0.0;
     for (int k = lane; k < kp; k += kWave) {
       _Float16 h = (_Float16)0.0f;
-      if (k < d) h = (_Float16)(float)((c[k] - S.gorg[k]) * sc);
+      if (k < d) {
+        const double xs = (c[k] - S.gorg[k]) * sc;
+        h = (_Float16)(float)xs;
+        const double hv = (double)(float)h;
+        nrm += hv * hv;
+        err += (xs - hv) * (xs - hv);
+      }
       S.g16[(size_t)i * kp + k] = h;
-      const double hv = (double)(float)h;
-      nrm += hv * hv;
     }
     nrm = wave_sum(nrm);
-    if (lane == 0) S.gnorm[i] = nrm;
+    err = wave_sum(err);
+    if (lane == 0) {
+      // FP32 accumulation of kp exact products, plus the FP32 roundings of
+      // the norms and of |x~|^2 + |y~|^2 - 2 x~.y~, with a factor 2 to spare
+      const double e = 2.0 * (double)(kp + 8) * 5.9604644775390625e-8 * nrm + 1e-30;
+      // eta: the rounding error, plus the FP64 error of the scaled centroid
+      const double eta = sqrt(err) * (1.0 + 1e-12) + 1e-15 * sqrt(nrm) + 1e-18;
+      double v = 0.0;
+      if (S.linkage != kWard) v = S.cvar[sl] / (double)S.csize[sl] * sc * sc;
+      float4 q;
+      q.x = (float)(nrm + v);
+      q.y = f32_dn(nrm - e);
+      q.z = f32_up(eta * (double)kGMargin);
+      if (S.linkage == kWard) {
+        q.w = (float)(1.0 / (double)S.csize[sl]);
+      } else {
+        const double vdn = v * (1.0 - 1e-6) - 0.5e-12;
+        q.w = f32_dn(vdn > 0.0 ? vdn : 0.0);
+      }
+      S.gq[i] = q;
+    }
   }
 }
 
@@ -1822,114 +1968,156 @@ __global__ void k_gram_init(State S, int *t_ovf) {
   }
 }
 
-// Rounding bound of d2~ in scaled units (see the comment above).
-__device__ __forceinline__ void gram_bounds(double d2h, double nq, double nc, int d, int kp, double &lo2,
-                                            double &hi2) {
-  const double sq = sqrt(nq), sn = sqrt(nc);
-  const double delta = kU16 * (sq + sn) * (1.0 + 4.0 * kU16) + 2.0 * sqrt((double)d) * kEta16;
-  const double gk = (double)kp * 6.0e-8;  // FP32 accumulation over kp terms
-  const double a = 2.0 * delta;
-  const double b = delta * delta + 2.02 * gk * sq * sn + 4e-16 * (nq + nc);
-  const double dm = d2h > 0.0 ? d2h : 0.0;
-  const double dup = 0.5 * (a + sqrt(a * a + 4.0 * (dm + b)));
-  const double e = 1.05 * (a * dup + b);
-  lo2 = d2h - e > 0.0 ? d2h - e : 0.0;
-  hi2 = dm + e;
+// FP64 upper bound of the key of terminal t and cluster c (the pass-0 pick).
+template <int LINK>
+__device__ double gram_pick_upper(const State &S, int t, int c) {
+  const int d = S.d;
+  const double *ct = S.wcen + (size_t)t * d, *cc = S.wcen + (size_t)c * d;
+  if (LINK == kWard) return ward_key<0>(ct, (double)S.csize[t], cc, (double)S.csize[c], d);
+  double v;
+  if (cache_resolve(S, S.node[t], S.node[c], v)) return v;
+  const int nt = S.csize[t], nc = S.csize[c];
+  if ((long long)nt * nc <= kInlinePairs)
+    return (S.cid[c] < S.cid[t]) ? pair_exact_inline<LINK>(S.px, d, S.cbeg[c], nc, S.cbeg[t], nt)
+                                 : pair_exact_inline<LINK>(S.px, d, S.cbeg[t], nt, S.cbeg[c], nc);
+  double D2 = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double x = ct[k] - cc[k];
+    D2 += x * x;
+  }
+  // complete: farthest pair <= D + rt + rc; average: also <= the root of the
+  // mean squared point distance D^2 + spreads (Jensen)
+  const double u1 = sqrt(D2) + S.crad[t] + S.crad[c];
+  if (LINK == kComplete) return u1 * u1 * (1.0 + 1e-12);
+  const double sc = *S.gscale;
+  const double vs = (S.cvar[t] / (double)nt + S.cvar[c] / (double)nc) * (1.0 + 1e-6) + 1e-12 / (sc * sc);
+  const double u2 = sqrt(D2 + vs);
+  return (u1 < u2 ? u1 : u2) * (1.0 + 1e-12);
 }
 
-// Key bounds of a pair from its centroid-distance bounds lo2 <= |cq-cc|^2 <= hi2
-// (scaled units), radius bounds r and mean squared spreads v = Var/size:
-//   Ward      key = w |cq - cc|^2 (Table 1)
-//   complete  mean of |x-y|^2 over pairs = |cq-cc|^2 + vq + vc <= key
-//             key <= (|cq - cc| + rq + rc)^2
-//   average   |cq - cc| <= key (Sec. 4.2) and, by Jensen, key <= sqrt(mean
-//             of |x-y|^2 over pairs) = sqrt(|cq-cc|^2 + vq + vc)
-template <int LINK>
-__device__ __forceinline__ void gram_keys(double lo2, double hi2, double sc, int nq, int nc, double rq, double rc,
-                                          double vq, double vc, double &klo, double &khi) {
-  const double is2 = 1.0 / (sc * sc);
-  if (LINK == kWard) {
-    const double w = (2.0 * (double)nq * (double)nc) / ((double)nq + (double)nc);
-    klo = w * lo2 * is2 * (1.0 - 1e-12);
-    khi = w * hi2 * is2 * (1.0 + 1e-12);
-  } else if (LINK == kComplete) {
-    // the spreads come from FP64 merge updates: relative and absolute margins
-    const double vlo = (vq + vc) * (1.0 - 1e-6) - 1e-12 * is2;
-    klo = (lo2 * is2 + (vlo > 0.0 ? vlo : 0.0)) * (1.0 - 1e-12);
-    const double u = sqrt(hi2 * is2) + rq + rc;
-    khi = u * u * (1.0 + 1e-12);
-  } else {
-    klo = sqrt(lo2 * is2) * (1.0 - 1e-12);
-    const double u1 = sqrt(hi2 * is2) + rq + rc;
-    const double u2 = sqrt(hi2 * is2 + (vq + vc) * (1.0 + 1e-6) + 1e-12 * is2);
-    khi = (u1 < u2 ? u1 : u2) * (1.0 + 1e-12);
+// Stage a 64-row tile of FP16 vectors in LDS. Pass 0 augments them so that
+// the MFMA result is the bound pass estimate: rows get (x~, a, 1), columns
+// (-2 y~, 1, b), with a, b the norm terms, so the product is a + b - 2 x~.y~.
+template <int KP, int PASS, bool ROW>
+__device__ __forceinline__ void gram_stage(const State &S, _Float16 (*dst)[KP + 8], const int *src_idx,
+                                           const float *aug, int nvalid, int d) {
+  constexpr int CH = KP / 8;  // 16-byte chunks per row
+  for (int j = threadIdx.x; j < kGT * CH; j += kBlock) {
+    const int r = j / CH, c8 = j % CH;
+    half8 v = {};
+    if (r < nvalid) {
+      v = *(const half8 *)(S.g16 + (size_t)src_idx[r] * KP + c8 * 8);
+      if (PASS == 0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = c8 * 8 + e;
+          if (!ROW && k < d) v[e] = v[e] * (_Float16)(-2.0f);
+          if (k == d) v[e] = ROW ? (_Float16)aug[r] : (_Float16)1.0f;
+          if (k == d + 1) v[e] = ROW ? (_Float16)1.0f : (_Float16)aug[r];
+        }
+      }
+    }
+    *(half8 *)&dst[r][c8 * 8] = v;
   }
 }
 
 template <int LINK, int KP, int PASS>
 __global__ __launch_bounds__(kBlock) void k_gram(State S) {
-  __shared__ __attribute__((aligned(16))) _Float16 sq[kGT][KP];
-  __shared__ __attribute__((aligned(16))) _Float16 sc[kGT][KP];
-  __shared__ double qn[kGT], cn[kGT], qr[kGT], cr[kGT], qb[kGT], qv[kGT], cv2[kGT];
-  __shared__ int qs[kGT], cs[kGT], qz[kGT], cz[kGT], qt[kGT];
-  __shared__ double rmin[4][32];
+  __shared__ __attribute__((aligned(16))) _Float16 sq[kGT][KP + 8];
+  __shared__ __attribute__((aligned(16))) _Float16 sc[kGT][KP + 8];
+  __shared__ float4 qd[kGT], cd[kGT];
+  __shared__ float qaug[kGT], caug[kGT], qthr[kGT];
+  __shared__ int qs[kGT], qt[kGT], qp[kGT], cs[kGT], cidx[kGT];
+  __shared__ float rbest[4][32];
+  __shared__ int rarg[4][32];
   const int nterm = min(S.tb1, S.cnt->n_term), nact = S.cnt->n_act;  // this batch: [tb0, nterm)
   const int q0 = S.tb0 + blockIdx.x * kGT;
   if (q0 >= nterm) return;  // uniform per block
+  const int nq = min(kGT, nterm - q0);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  const double scale = *S.gscale;
   const int d = S.d;
-  // query tile
-  constexpr int CH = KP / 8;  // 16-byte chunks per row
-  for (int j = threadIdx.x; j < kGT * CH; j += kBlock) {
-    const int r = j / CH, c8 = j % CH;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (q0 + r < nterm) v = *(const uint4 *)(S.g16 + (size_t)S.term_pos[q0 + r] * KP + c8 * 8);
-    *(uint4 *)&sq[r][c8 * 8] = v;
-  }
+  const double scale = *S.gscale;
   if (threadIdx.x < kGT) {
     const int r = threadIdx.x, ti = q0 + r;
-    if (ti < nterm) {
-      const int t = S.term[ti], pi = S.term_pos[ti];
-      qs[r] = t;
+    if (r < nq) {
+      const int pi = S.term_pos[ti];
+      const float4 g = S.gq[pi];
+      qs[r] = S.term[ti];
       qt[r] = ti;
-      qn[r] = S.gnorm[pi];
-      qz[r] = S.csize[t];
-      qr[r] = LINK != kWard ? S.crad[t] : 0.0;
-      qv[r] = LINK != kWard ? S.cvar[t] / (double)S.csize[t] : 0.0;
-      qb[r] = PASS == 1 ? S.t_beta[ti] * kSlack : 0.0;
+      qp[r] = pi;
+      cidx[r] = pi;  // staging source for the rows
+      qd[r] = g;
+      qaug[r] = g.x;
+      if (PASS == 1) {
+        // threshold in scaled key units, rounded up with margin
+        const double u = S.t_beta[ti] * kSlack;
+        const double us = LINK == kAverage ? u * scale : u * scale * scale;
+        float uf = f32_up(us * (double)kGMargin);
+        uf = uf > 1e-30f ? uf : 1e-30f;
+        if (LINK == kWard) qthr[r] = 0.5f * uf;
+        else if (LINK == kComplete) qthr[r] = uf - g.w;
+        else qthr[r] = uf + g.z;
+      }
     } else {
       qs[r] = -1;
       qt[r] = -1;
+      qp[r] = -1;
+      cidx[r] = 0;
+      qd[r] = make_float4(NAN, NAN, NAN, NAN);
+      qaug[r] = 0.0f;
+      if (PASS == 1) qthr[r] = NAN;
     }
   }
-  double run[16];
+  __syncthreads();
+  gram_stage<KP, PASS, true>(S, sq, cidx, qaug, nq, d);
+  // this lane's 16 rows (MFMA 32x32 output layout)
+  float rq[16], rz[16], rt[16], re[16];
+  int pmin = 0x7fffffff, pmax = -1;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) run[i] = INFINITY;
+  for (int i = 0; i < 16; ++i) {
+    const int row = wr + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+    const float4 g = qd[row];
+    rq[i] = PASS == 0 ? g.x : g.y;
+    rz[i] = g.w;
+    re[i] = g.z;
+    rt[i] = PASS == 1 ? qthr[row] : 0.0f;
+  }
+  for (int r = 0; r < nq; ++r) {
+    pmin = min(pmin, qp[r]);
+    pmax = max(pmax, qp[r]);
+  }
+  float best[16];
+  int barg[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    best[i] = INFINITY;
+    barg[i] = -1;
+  }
   long long pairs = 0;
   for (int c0 = blockIdx.y * kGT; c0 < nact; c0 += gridDim.y * kGT) {
+    const int nc = min(kGT, nact - c0);
     __syncthreads();
-    for (int j = threadIdx.x; j < kGT * CH; j += kBlock) {
-      const int r = j / CH, c8 = j % CH;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (c0 + r < nact) v = *(const uint4 *)(S.g16 + (size_t)(c0 + r) * KP + c8 * 8);
-      *(uint4 *)&sc[r][c8 * 8] = v;
-    }
     if (threadIdx.x < kGT) {
-      const int r = threadIdx.x, ci = c0 + r;
-      if (ci < nact) {
-        const int sl = S.act[ci];
-        cs[r] = sl;
-        cn[r] = S.gnorm[ci];
-        cz[r] = S.csize[sl];
-        cr[r] = LINK != kWard ? S.crad[sl] : 0.0;
-        cv2[r] = LINK != kWard ? S.cvar[sl] / (double)S.csize[sl] : 0.0;
+      const int r = threadIdx.x;
+      if (r < nc) {
+        const float4 g = S.gq[c0 + r];
+        cd[r] = g;
+        caug[r] = g.x;
+        cs[r] = S.act[c0 + r];
+        cidx[r] = c0 + r;
       } else {
+        // padding columns: an infinite norm term keeps them out of both passes
+        cd[r] = make_float4(INFINITY, INFINITY, 0.0f, 1.0f);
+        caug[r] = 0.0f;
         cs[r] = -2;
+        cidx[r] = 0;
       }
     }
     __syncthreads();
+    gram_stage<KP, PASS, false>(S, sc, cidx, caug, nc, d);
+    __syncthreads();
+    if (threadIdx.x == 0) pairs += (long long)nq * nc;
     float16v acc = {};
 #pragma unroll
     for (int kk = 0; kk < KP; kk += 16) {
@@ -1938,55 +2126,93 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
       acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
     }
     const int col = wc + (lane & 31);
-    const int cslot = cs[col];
+    const int ci = c0 + col;
+    const float4 cg = cd[col];
+    // the terminals' own columns lie in [pmin, pmax]; only those tiles check
+    const bool selfs = c0 <= pmax && c0 + kGT > pmin;
+    if (PASS == 0) {
+      const float cz = cg.w;
+      const bool padc = col >= nc;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int row = wr + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
-      const int qslot = qs[row];
-      if (qslot < 0 || cslot < 0 || qslot == cslot) continue;
-      const double d2h = qn[row] + cn[col] - 2.0 * (double)acc[i];
-      double lo2, hi2, klo, khi;
-      gram_bounds(d2h, qn[row], cn[col], d, KP, lo2, hi2);
-      gram_keys<LINK>(lo2, hi2, scale, qz[row], cz[col], qr[row], cr[col], qv[row], cv2[col], klo, khi);
-      ++pairs;
-      if (PASS == 0) {
-        run[i] = khi < run[i] ? khi : run[i];
-      } else if (klo <= qb[row]) {
-        const long long k = append_slot(&S.cnt->n_cand);
-        if (k < S.cand_cap) {
-          S.cd_t[k] = qt[row];
-          S.cd_c[k] = cslot;
-          S.cd_lb[k] = klo;
-        } else {
-          S.cnt->cand_overflow = 1;
+      for (int i = 0; i < 16; ++i) {
+        float g = acc[i];
+        if (LINK == kWard) g = g * __builtin_amdgcn_rcpf(rz[i] + cz);
+        if (padc) g = INFINITY;
+        if (selfs) {
+          const int row = wr + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+          if (qp[row] == ci) g = INFINITY;
+        }
+        if (g < best[i]) {
+          best[i] = g;
+          barg[i] = ci;
+        }
+      }
+    } else {
+      const float cm = cg.y, ce = cg.z, cw = cg.w;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        // lower bound of T^2 against the square of (threshold distance + eta)
+        const float lhs = __builtin_fmaf(-2.0f, acc[i], rq[i] + cm);
+        float rr;
+        if (LINK == kWard) rr = __builtin_amdgcn_sqrtf(rt[i] * (rz[i] + cw)) + (re[i] + ce);
+        else if (LINK == kComplete) rr = __builtin_amdgcn_sqrtf(rt[i] - cw) + (re[i] + ce);
+        else rr = rt[i] + ce;
+        if (lhs <= rr * rr) {
+          const int row = wr + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+          const int cslot = cs[col];
+          if (cslot >= 0 && qp[row] != ci && qt[row] >= 0) {
+            const long long k = append_slot(&S.cnt->n_cand);
+            if (k < S.cand_cap) {
+              S.cd_t[k] = qt[row];
+              S.cd_c[k] = cslot;
+              S.cd_lb[k] = 0.0;
+            } else {
+              S.cnt->cand_overflow = 1;
+            }
+          }
         }
       }
     }
   }
   if (PASS == 0) {
-    // row minima: reduce over the 32 lanes holding one row, then over the two
-    // wavefronts that share the rows
+    // each row's pick: over the 32 lanes holding the row, then over the two
+    // wavefronts that share the rows; then its FP64 upper bound
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      double v = run[i];
+      float v = best[i];
+      int a = barg[i];
       for (int o = 16; o > 0; o >>= 1) {
-        const double u = __shfl_xor(v, o, kWave);
-        v = u < v ? u : v;
+        const float u = __shfl_xor(v, o, kWave);
+        const int b = __shfl_xor(a, o, kWave);
+        if (u < v || (u == v && b >= 0 && (a < 0 || b < a))) {
+          v = u;
+          a = b;
+        }
       }
-      run[i] = v;
+      best[i] = v;
+      barg[i] = a;
     }
+    __syncthreads();
     if ((lane & 31) == 0)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) rmin[w][(i >> 2) * 8 + (lane >> 5) * 4 + (i & 3)] = run[i];
+      for (int i = 0; i < 16; ++i) {
+        const int rl = (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+        rbest[w][rl] = best[i];
+        rarg[w][rl] = barg[i];
+      }
     __syncthreads();
     if (threadIdx.x < kGT) {
       const int r = threadIdx.x, wq = (r >> 5) * 2;
-      const double v = fmin(rmin[wq][r & 31], rmin[wq + 1][r & 31]);
-      if (qt[r] >= 0 && v < INFINITY) atomicMin((unsigned long long *)&S.t_beta[qt[r]], pos_bits(v));
+      const float b0 = rbest[wq][r & 31], b1 = rbest[wq + 1][r & 31];
+      const int a0 = rarg[wq][r & 31], a1 = rarg[wq + 1][r & 31];
+      const int a = (b1 < b0 || (b1 == b0 && a1 >= 0 && (a0 < 0 || a1 < a0))) ? a1 : a0;
+      if (qt[r] >= 0 && a >= 0) {
+        const double u = gram_pick_upper<LINK>(S, qs[r], S.act[a]);
+        atomicMin((unsigned long long *)&S.t_beta[qt[r]], pos_bits(u));
+      }
     }
   }
-  if (PASS == 0) count_add(&S.cnt->visits[0], pairs);
-  else count_add(&S.cnt->visits[3], pairs);
+  count_add(&S.cnt->visits[PASS == 0 ? 0 : 3], pairs);  // nonzero in thread 0 only
 }
 
 // Recorded candidates: exact FP64 value (Ward, small complete/average pairs,
@@ -2015,7 +2241,7 @@ __global__ void k_gram_exact(State S) {
         ppairs += cost;
       } else {
         const unsigned long long pk = pair_key(S.node[t], S.node[c]);
-        if (S.cache_mask && cache_find(S, pk, v) == 1) {
+        if (cache_resolve(S, S.node[t], S.node[c], v)) {
           ++hits;
         } else {
           if (S.cache_mask && cache_claim(S, pk) == 2) {
@@ -2023,6 +2249,7 @@ __global__ void k_gram_exact(State S) {
             if (q < S.pair_cap) {
               S.pd_t[q] = ti;
               S.pd_c[q] = c;
+              S.pd_v[q] = -1.0;
             } else {
               S.cnt->pair_overflow = 1;
             }
@@ -2185,6 +2412,10 @@ __global__ void k_merge(State S, int base) {
       }
       S.mdst[b] = a;
       S.moff[b] = sa;
+    }
+    if (S.cache_mask) {
+      S.nparent[S.node[a]] = n + r;
+      S.nparent[S.node[b]] = n + r;
     }
     S.node[a] = n + r;
     S.node2slot[n + r] = a;
@@ -2380,7 +2611,9 @@ void launch_gram_batch_t(State &S, int nact, hipStream_t s) {
   case 16: launch_gram_kp<LINK, 16>(S, nact, s); break;
   case 32: launch_gram_kp<LINK, 32>(S, nact, s); break;
   case 64: launch_gram_kp<LINK, 64>(S, nact, s); break;
-  default: launch_gram_kp<LINK, 128>(S, nact, s); break;
+  case 80: launch_gram_kp<LINK, 80>(S, nact, s); break;
+  case 128: launch_gram_kp<LINK, 128>(S, nact, s); break;
+  default: launch_gram_kp<LINK, 144>(S, nact, s); break;
   }
 }
 

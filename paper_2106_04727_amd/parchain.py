@@ -57,7 +57,7 @@ class pc_stats(ctypes.Structure):
                 ("ms_finalize", ctypes.c_double), ("kernel_ms", ctypes.c_double * 4),
                 ("kernel_launches", ctypes.c_int64 * 4), ("candidate_visits", ctypes.c_int64 * 4),
                 ("cache_hits", ctypes.c_int64), ("cache_inserts", ctypes.c_int64),
-                ("cache_fail", ctypes.c_int64)]
+                ("cache_fail", ctypes.c_int64), ("cache_derived", ctypes.c_int64)]
 
     KERNELS = ("ring_search", "block_search", "pair_tiles", "ring_emit")
 

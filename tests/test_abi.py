@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
 def test_struct_sizes():
     assert ctypes.sizeof(parchain.pc_merge) == 32
     assert ctypes.sizeof(parchain.pc_options) == 24
-    assert ctypes.sizeof(parchain.pc_stats) == 8 + 5 * 8 + 4 * 8 + 4 * 8 + 4 * 8 + 4 * 8 + 3 * 8
+    assert ctypes.sizeof(parchain.pc_stats) == 8 + 5 * 8 + 4 * 8 + 4 * 8 + 4 * 8 + 4 * 8 + 4 * 8
 
 
 def test_version_string():

@@ -102,7 +102,7 @@ def test_prune_on_equals_off(pc, link):
     x = synth.blobs(1500, 2, 6, 0.05, 21)
     Za = pc.hac(x, link, prune=True)
     Zb = pc.hac(x, link, prune=False)
-    assert np.array_equal(Za, Zb)
+    assert same_rows(Za, Zb, link)
 
 
 @pytest.mark.parametrize("link", LINKS)
@@ -168,23 +168,35 @@ def test_overflow_paths(pc, link, monkeypatch):
     Z1 = pc.hac(x, link)
     monkeypatch.setenv("PC_TEST_PAIR_CAP", "8")
     Z2 = pc.hac(x, link)
-    assert np.array_equal(Z0, Z1) and np.array_equal(Z0, Z2)
+    assert same_rows(Z0, Z1, link) and same_rows(Z0, Z2, link)
     Zo, _ = oracle.nnchain(x, link, threads=8)
     assert _trees.same_tree(Z0, Zo, 4000, rtol=RTOL[link])
+
+
+def same_rows(Za, Zb, link):
+    """Identical rows; average-linkage heights may differ in the last bits
+    when one run takes a value from cached parts (Lance-Williams, Sec. 5) and
+    the other sums the point distances."""
+    if link != "average":
+        return np.array_equal(Za, Zb)
+    return (np.array_equal(Za[:, [0, 1, 3]], Zb[:, [0, 1, 3]])
+            and np.allclose(Za[:, 2], Zb[:, 2], rtol=1e-12, atol=0.0))
 
 
 @pytest.mark.parametrize("link", ["complete", "average"])
 def test_cache_on_equals_off(pc, link, monkeypatch):
     """The cluster-pair cache (Alg. 4, Sec. 5) only avoids recomputation: rows
-    are identical with it off, on, and squeezed into a tiny table."""
+    are the same with it off, on, and squeezed into a tiny table. Values are
+    also combined from cached parts of merged clusters (Table 2 rules)."""
     x = synth.blobs(6000, 2, 20, 0.02, 41)
     Z0, s0 = pc.hac(x, link, cache_slots=0, return_stats=True)
     Z1, s1 = pc.hac(x, link, cache_slots=64, return_stats=True)
     assert s0["cache_hits"] == 0 and s1["cache_inserts"] > 0
-    assert np.array_equal(Z0, Z1)
+    assert s1["cache_derived"] > 0
+    assert same_rows(Z0, Z1, link)
     monkeypatch.setenv("PC_TEST_CACHE_CAP", "512")
     Z2 = pc.hac(x, link, cache_slots=64)
-    assert np.array_equal(Z0, Z2)
+    assert same_rows(Z0, Z2, link)
     Zo, _ = oracle.nnchain(x, link, threads=8)
     assert _trees.same_tree(Z0, Zo, 6000, rtol=RTOL[link])
 
@@ -193,7 +205,18 @@ def test_cache_d10_average(pc):
     x = synth.blobs(3000, 10, 30, 0.02, 42)
     Z0 = pc.hac(x, "average", cache_slots=0)
     Z1, st = pc.hac(x, "average", cache_slots=64, return_stats=True)
-    assert np.array_equal(Z0, Z1) and st["cache_hits"] > 0
+    assert same_rows(Z0, Z1, "average") and st["cache_hits"] > 0
+
+
+@pytest.mark.parametrize("link", ["complete", "average"])
+def test_cache_high_dim(pc, link):
+    """d = 64 (Gram search): cached and combined values against none."""
+    x = synth.sphere_blobs(2000, 64, 20, 0.1, 43)
+    Z0 = pc.hac(x, link, cache_slots=0)
+    Z1, st = pc.hac(x, link, cache_slots=64, return_stats=True)
+    assert same_rows(Z0, Z1, link) and st["cache_derived"] > 0
+    Zo, _ = oracle.nnchain(x, link, threads=8)
+    assert _trees.same_tree(Z1, Zo, 2000, rtol=RTOL[link])
 
 
 @pytest.mark.parametrize("link", LINKS)
@@ -204,7 +227,7 @@ def test_gram_record_overflow(pc, link, monkeypatch):
     Z0 = pc.hac(x, link)
     monkeypatch.setenv("PC_TEST_CAND_CAP", "64")
     Z1 = pc.hac(x, link)
-    assert np.array_equal(Z0, Z1)
+    assert same_rows(Z0, Z1, link)
 
 
 @pytest.mark.parametrize("link", LINKS)
@@ -217,6 +240,6 @@ def test_gram_batches(pc, link, monkeypatch):
     Z1 = pc.hac(x, link)
     monkeypatch.setenv("PC_TEST_CAND_CAP", "256")
     Z2 = pc.hac(x, link)
-    assert np.array_equal(Z0, Z1) and np.array_equal(Z0, Z2)
+    assert same_rows(Z0, Z1, link) and same_rows(Z0, Z2, link)
     Zo, _ = oracle.nnchain(x, link, threads=8)
     assert _trees.same_tree(Z0, Zo, 2500, rtol=RTOL[link])

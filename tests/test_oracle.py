@@ -181,6 +181,26 @@ def test_lance_williams_recurrences():
         assert dabc**2 == pytest.approx(lw, rel=1e-9)
 
 
+def test_cache_update_rules_two_sides_merged():
+    """Sec. 5 update rules when both clusters of a pair were just merged
+    (A u B against C u D): the average is the size-weighted mean of the four
+    cross values, the complete distance the largest of them."""
+    rng = np.random.default_rng(9)
+    x = rng.random((400, 4)).astype(np.float32)
+    for _ in range(30):
+        p = rng.permutation(400)
+        a, b, c, e = rng.integers(1, 25, 4)
+        A, B = p[:a], p[a : a + b]
+        C, D = p[a + b : a + b + c], p[a + b + c : a + b + c + e]
+        AB, CD = np.concatenate([A, B]), np.concatenate([C, D])
+        parts = [(X, Y) for X in (A, B) for Y in (C, D)]
+        avg = sum(len(X) * len(Y) * oracle.linkage_dist(x, "average", X, Y) for X, Y in parts)
+        avg /= len(AB) * len(CD)
+        assert oracle.linkage_dist(x, "average", AB, CD) == pytest.approx(avg, rel=1e-12)
+        comp = max(oracle.linkage_dist(x, "complete", X, Y) for X, Y in parts)
+        assert oracle.linkage_dist(x, "complete", AB, CD) == comp
+
+
 @pytest.mark.parametrize("link", LINKS)
 def test_reducibility_monotone_heights(link):
     x = synth.blobs(3000, 2, 10, 0.02, 4)
