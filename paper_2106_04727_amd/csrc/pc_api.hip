@@ -99,6 +99,10 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   S.gkp = kp;
   S.g16 = c.take<_Float16>(gram ? n * kp : 1);
   S.gq = c.take<float4>(gram ? n : 1);
+  S.p16 = gram && pts ? c.take<_Float16>(n * kp) : nullptr;
+  S.pq = c.take<float4>(gram && pts ? n : 1);
+  S.porg = c.take<double>(gram ? d : 1);
+  S.pscale = c.take<double>(1);
   S.gorg = c.take<double>(gram ? d : 1);
   S.gmin = c.take<unsigned long long>(gram ? d : 1);
   S.gmax = c.take<unsigned long long>(gram ? d : 1);
@@ -285,15 +289,21 @@ static pc_status grow_tiles(pc_context *ctx, State &S, long long cap) {
 
 static pc_status grow_cand(pc_context *ctx, State &S, long long cap) {
   if (cap > kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round needs more than 2^30 recorded candidates");
-  const size_t per = 2 * sizeof(int) + 2 * sizeof(double);
+  // per candidate: lower bound, value (f64), tile prefix (i64), point ranges
+  // (int4), terminal, cluster, small-list entry (i32)
+  const size_t per = 2 * sizeof(double) + sizeof(long long) + sizeof(int4) + 4 * sizeof(int);
   HIPCHK(grow(ctx->cand, (size_t)cap * per + 1024));
   const long long cc = (long long)((ctx->cand.bytes - 1024) / per);
   S.cand_cap = cc;
   S.cd_lb = (double *)ctx->cand.p;
   S.cd_v = S.cd_lb + cc;
-  S.cd_t = (int *)(S.cd_v + cc);
+  S.cd_tile0 = (long long *)(S.cd_v + cc);
+  S.cd_desc = (int4 *)(S.cd_tile0 + cc);
+  S.cd_t = (int *)(S.cd_desc + cc);
   S.cd_c = S.cd_t + cc;
-  return PC_OK;
+  S.cd_small = S.cd_c + cc;
+  S.cd_scr = S.cd_small + cc;
+  return grow_part(ctx, S, std::max<long long>(cc, 2LL * S.n + 64));
 }
 
 pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int points_on_device,
@@ -484,6 +494,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
       // Gram search: terminals in batches, each with a bounded candidate record
       HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+        take_times();  // a timing slot may be reused within the round
       const int nterm = h.n_term;
       long long tb = gram_batch > 0 ? std::min<long long>(gram_batch, nterm) : nterm;
       for (int t0 = 0; t0 < nterm;) {
@@ -494,6 +505,15 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        take_times();  // a timing slot may be reused within the round
+        if (!h.cand_overflow) {
+          // screening and exact values (or claims) of the recorded candidates
+          launch_gram_refine(S, (int)std::min<long long>(h.n_cand, S.cand_cap), s);
+          HIPCHK(hipGetLastError());
+          HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+        take_times();  // a timing slot may be reused within the round
+        }
         const bool pover = h.pair_overflow || h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap;
         if (h.cand_overflow || pover) {
           // redo this batch: larger buffers while they stay within the limit,

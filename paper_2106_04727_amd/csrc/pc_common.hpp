@@ -37,9 +37,7 @@ enum Linkage { kComplete = 0, kAverage = 1, kWard = 2 };
 
 // ---------------------------------------------------------------- helpers --
 // Reserve one slot of a 64-bit append counter; returns the slot index.
-__device__ __forceinline__ long long append_slot(long long *counter) {
-  return (long long)atomicAdd((unsigned long long *)counter, 1ull);
-}
+
 __device__ __forceinline__ unsigned long long ordered_bits(double v) {
   // monotone map of doubles to unsigned 64-bit integers (for atomic min/max)
   unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -59,6 +57,17 @@ __device__ __forceinline__ double pos_from_bits(unsigned long long b) {
 __device__ __forceinline__ unsigned long long lanemask_lt() {
   const int lane = threadIdx.x & (kWave - 1);
   return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+// Next free index of an append-only list: one atomic per wavefront for all
+// lanes that call it together (every caller passes the same counter).
+__device__ __forceinline__ long long append_slot(long long *counter) {
+  const unsigned long long m = __ballot(1);
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  const int lane = threadIdx.x & (kWave - 1);
+  long long base = 0;
+  if (lane == leader) base = (long long)atomicAdd((unsigned long long *)counter, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader, kWave);
+  return base + __popcll(m & lanemask_lt());
 }
 
 // --------------------------------------------------------- device state ----
@@ -100,6 +109,10 @@ struct Counters {
   long long cache_inserts;
   long long cache_fail;
   long long cache_derived;
+  long long n_ctiles;  // interval tiles of the current batch
+  long long n_small;   // small candidates of the current batch
+  long long n_scr;     // screened candidates of the current batch
+  int n_scr32, pad_scr;
 };
 
 // All device arrays of one clustering call. Slots are storage indices of
@@ -186,6 +199,16 @@ struct State {
   int gkp;              // padded K (multiple of 16)
   _Float16 *g16;        // n x gkp, in active-list order
   float4 *gq;  // per active item: pass-0 norm term, rigorous norm, rounding error, size/spread term
+  // interval screening (complete/average): FP16 points in their current
+  // places and their terms (|x~|^2, e, eta), the fixed point scaling, and the
+  // candidates' tile prefix
+  _Float16 *p16;
+  float4 *pq;
+  double *porg, *pscale;
+  long long *cd_tile0;
+  int *cd_small;  // small candidates (exact now)
+  int4 *cd_desc;  // screened candidates (dense): row begin, rows, column begin, columns
+  int *cd_scr;    // screened candidates (dense): candidate index
   int *nparent;  // node -> parent node (-1: none yet); kept when the cache is on
   double *gorg;         // d
   unsigned long long *gmin, *gmax;  // per-dimension ordered bits of the centroid range
@@ -220,6 +243,7 @@ void launch_round(State &S, int round, int nact_host, hipStream_t s, bool &need_
 void launch_emit_fallback(State &S, int nact_host, hipStream_t s);
 void launch_gram_keys(State &S, hipStream_t s);
 void launch_gram_batch(State &S, int nact_host, hipStream_t s);
+void launch_gram_refine(State &S, int ncand, hipStream_t s);
 void launch_cache_clear(State &S, unsigned long long *keys, unsigned long long *vals,
                         unsigned long long mask, hipStream_t s);
 void launch_cache_rebuild(State &S, const unsigned long long *okeys, const unsigned long long *ovals,

@@ -116,6 +116,9 @@ __global__ void k_reset_round(Counters *c) {
 
 // per Gram batch: the append counters start empty
 __global__ void k_reset_batch(Counters *c) {
+  c->n_small = 0;
+  c->n_scr = 0;
+  c->n_scr32 = 0;
   c->n_cand = 0;
   c->n_pairs = 0;
   c->n_pend = 0;
@@ -1444,6 +1447,31 @@ __device__ __forceinline__ void pair_orient(const State &S, int p, int &begR, in
   nS = S.csize[q];
 }
 
+// Tile walks: block b takes the contiguous tiles [a, e) of `total` and finds
+// the owner of its first tile by binary search over the exclusive prefix
+// `start` (entries with no tiles share the next entry's start); later tiles
+// advance the owner.
+__device__ __forceinline__ void tile_share(long long total, long long &a, long long &e) {
+  const long long per = (total + gridDim.x - 1) / gridDim.x;
+  a = (long long)blockIdx.x * per;
+  e = a + per < total ? a + per : total;
+}
+
+__device__ __forceinline__ int tile_owner(const long long *start, int cnt, long long tile) {
+  int lo = 0, hi = cnt - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int tile_advance(const long long *start, int cnt, int i, long long tile) {
+  while (i + 1 < cnt && start[i + 1] <= tile) ++i;
+  return i;
+}
+
 __global__ void k_pair_tiles(State S, long long *ntl) {
   const int np = (int)min(S.cnt->n_pairs, S.pair_cap);
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
@@ -1468,18 +1496,15 @@ __global__ __launch_bounds__(kBlock) void k_tiles_avg(State S, long long ntiles)
   const int d = S.d;
   long long ppairs = 0;
   const long long ngroups = (ntiles + kW - 1) / kW;
-  for (long long gg = blockIdx.x; gg < ngroups; gg += gridDim.x) {
+  long long ga, ge;
+  tile_share(ngroups, ga, ge);
+  int p = ga < ge && ga * kW + w < ntiles ? tile_owner(S.pr_tile0, np, ga * kW + w) : 0;
+  for (long long gg = ga; gg < ge; ++gg) {
     const long long gt = gg * kW + w;
     const bool active = gt < ntiles;
     int br = 0, r0 = 0, nrow = 0, col = 0, ns = 0, bs = 0;
     if (active) {
-      int lo = 0, hi = np - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (S.pr_tile0[mid] <= gt) lo = mid;
-        else hi = mid - 1;
-      }
-      const int p = lo;
+      p = tile_advance(S.pr_tile0, np, p, gt);
       int nr;
       pair_orient(S, p, br, nr, bs, ns);
       const long long local = gt - S.pr_tile0[p];
@@ -1590,15 +1615,14 @@ __global__ __launch_bounds__(kBlock) void k_filter_comp(State S, long long nchun
   __shared__ double vtx[2][kSupDirs][2];  // enclosing polygons of R (0) and S (1), d == 2
   const int np = (int)min(S.cnt->n_pairs, S.pair_cap);
   const int d = S.d;
-  for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  long long ca, ce;
+  tile_share(nchunks, ca, ce);
+  int owner = 0;
+  if (threadIdx.x == 0 && ca < ce) owner = tile_owner(S.pr_cbase, np, ca);
+  for (long long ch = ca; ch < ce; ++ch) {
     if (threadIdx.x == 0) {
-      int lo = 0, hi = np - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (S.pr_cbase[mid] <= ch) lo = mid;
-        else hi = mid - 1;
-      }
-      sp = lo;
+      owner = tile_advance(S.pr_cbase, np, owner, ch);
+      sp = owner;
     }
     __syncthreads();
     const int p = sp;
@@ -1665,19 +1689,16 @@ __global__ __launch_bounds__(kBlock) void k_tiles_comp(State S) {
   const int d = S.d;
   long long ppairs = 0;
   const long long ngroups = (ntiles + kW - 1) / kW;
-  for (long long gg = blockIdx.x; gg < ngroups; gg += gridDim.x) {
+  long long ga, ge;
+  tile_share(ngroups, ga, ge);
+  int p = ga < ge && ga * kW + w < ntiles ? tile_owner(S.pr_tile0, np, ga * kW + w) : 0;
+  for (long long gg = ga; gg < ge; ++gg) {
     const long long gt = gg * kW + w;
     const bool active = gt < ntiles;
-    int p = 0, r0 = 0, nrow = 0, col = 0, ks = 0, nR = 0;
+    int r0 = 0, nrow = 0, col = 0, ks = 0, nR = 0;
     long long region = 0;
     if (active) {
-      int lo = 0, hi = np - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (S.pr_tile0[mid] <= gt) lo = mid;
-        else hi = mid - 1;
-      }
-      p = lo;
+      p = tile_advance(S.pr_tile0, np, p, gt);
       int r, q;
       pair_slots(S, p, r, q);
       nR = S.csize[r];
@@ -1732,6 +1753,99 @@ __global__ __launch_bounds__(kBlock) void k_tiles_comp(State S) {
     if (active && lane == 0) atomicMax((unsigned long long *)&S.pr_v[p], pos_bits(acc));
   }
   count_add(&S.cnt->point_pairs, ppairs);
+}
+
+// Exact tiles for 16 < d <= kGramMaxDim: one block per 64x64 tile, both point
+// sets staged in LDS (coordinate-major, FP32 as given), each thread a 4x4
+// block of pairs. Squared distances are summed over the coordinates in order
+// with separate multiply and add, as the oracle does. Average adds the roots
+// into the tile's sum; complete takes the largest square.
+template <int LINK>
+__global__ __launch_bounds__(kBlock) void k_tiles_hd(State S) {
+  __shared__ __attribute__((aligned(16))) float As[kGramMaxDim][kTile];
+  __shared__ __attribute__((aligned(16))) float Bs[kGramMaxDim][kTile];
+  __shared__ double red[kBlock / kWave];
+  const int np = (int)min(S.cnt->n_pairs, S.pair_cap);
+  const long long ntiles = S.cnt->n_tiles;
+  const int d = S.d;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  long long ppairs = 0;
+  long long ta, te;
+  tile_share(ntiles, ta, te);
+  int p = ta < te ? tile_owner(S.pr_tile0, np, ta) : 0;
+  for (long long gt = ta; gt < te; ++gt) {
+    p = tile_advance(S.pr_tile0, np, p, gt);
+    const long long local = gt - S.pr_tile0[p];
+    int nA, nB, begA = 0, begB = 0;
+    long long region = 0;
+    if (LINK == kAverage) {
+      pair_orient(S, p, begA, nA, begB, nB);
+    } else {
+      int r, q;
+      pair_slots(S, p, r, q);
+      nA = S.pr_kR[p];
+      nB = S.pr_kS[p];
+      region = S.pr_cbase[p] * kChunk;
+      begB = S.csize[r];  // column indices follow the row cluster's slots
+    }
+    const int ntc = (nB + kTile - 1) / kTile;
+    const int r0 = (int)(local / ntc) * kTile, c0 = (int)(local % ntc) * kTile;
+    const int nr = min(kTile, nA - r0), nc = min(kTile, nB - c0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < kTile * d; j += kBlock) {
+      const int i = j / d, k = j % d;
+      float a = 0.0f, b = 0.0f;
+      if (i < nr) {
+        const int pa = LINK == kAverage ? begA + r0 + i : S.fidx[region + r0 + i];
+        a = S.px[(size_t)pa * d + k];
+      }
+      if (i < nc) {
+        const int pb = LINK == kAverage ? begB + c0 + i : S.fidx[region + begB + c0 + i];
+        b = S.px[(size_t)pb * d + k];
+      }
+      As[k][i] = a;
+      Bs[k][i] = b;
+    }
+    __syncthreads();
+    double q[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) q[a][b] = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const float4 av = *(const float4 *)&As[k][ty * 4];
+      const float4 bv = *(const float4 *)&Bs[k][tx * 4];
+      const double ar[4] = {(double)av.x, (double)av.y, (double)av.z, (double)av.w};
+      const double br[4] = {(double)bv.x, (double)bv.y, (double)bv.z, (double)bv.w};
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double u = ar[a] - br[b];
+          q[a][b] += u * u;
+        }
+    }
+    double part = LINK == kAverage ? 0.0 : -1.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (ty * 4 + a >= nr || tx * 4 + b >= nc) continue;
+        if (LINK == kAverage) part += sqrt(q[a][b]);
+        else part = q[a][b] > part ? q[a][b] : part;
+      }
+    part = LINK == kAverage ? wave_sum(part) : wave_max(part);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double v = red[0];
+      for (int j = 1; j < kBlock / kWave; ++j) v = LINK == kAverage ? v + red[j] : (red[j] > v ? red[j] : v);
+      if (LINK == kAverage) S.tile_v[gt] = v;
+      else atomicMax((unsigned long long *)&S.pr_v[p], pos_bits(v));
+      ppairs += (long long)nr * nc;
+    }
+  }
+  count_add(&S.cnt->point_pairs, ppairs);  // nonzero in thread 0 only
 }
 
 // Per pair: finish the value, then WriteMin into its terminal's best value.
@@ -2149,6 +2263,8 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
       }
     } else {
       const float cm = cg.y, ce = cg.z, cw = cg.w;
+      const int cslot = cs[col];
+      unsigned rmask = 0;
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         // lower bound of T^2 against the square of (threshold distance + eta)
@@ -2157,19 +2273,40 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
         if (LINK == kWard) rr = __builtin_amdgcn_sqrtf(rt[i] * (rz[i] + cw)) + (re[i] + ce);
         else if (LINK == kComplete) rr = __builtin_amdgcn_sqrtf(rt[i] - cw) + (re[i] + ce);
         else rr = rt[i] + ce;
-        if (lhs <= rr * rr) {
+        rmask |= (lhs <= rr * rr ? 1u : 0u) << i;
+      }
+      if (cslot < 0) rmask = 0;
+      if (selfs && rmask) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
           const int row = wr + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
-          const int cslot = cs[col];
-          if (cslot >= 0 && qp[row] != ci && qt[row] >= 0) {
-            const long long k = append_slot(&S.cnt->n_cand);
-            if (k < S.cand_cap) {
-              S.cd_t[k] = qt[row];
-              S.cd_c[k] = cslot;
-              S.cd_lb[k] = 0.0;
-            } else {
-              S.cnt->cand_overflow = 1;
-            }
+          if (qp[row] == ci) rmask &= ~(1u << i);
+        }
+      }
+      // one atomic per wavefront and tile: exclusive prefix of the lanes' counts
+      if (__ballot(rmask != 0)) {
+        const int cnt = __popc(rmask);
+        int incl = cnt;
+        for (int o = 1; o < kWave; o <<= 1) {
+          const int y = __shfl_up(incl, o, kWave);
+          if (lane >= o) incl += y;
+        }
+        long long base = 0;
+        if (lane == kWave - 1 && incl > 0) base = (long long)atomicAdd((unsigned long long *)&S.cnt->n_cand, (unsigned long long)incl);
+        base = __shfl(base, kWave - 1, kWave);
+        long long k = base + incl - cnt;
+        while (rmask) {
+          const int i = __ffs(rmask) - 1;
+          rmask &= rmask - 1;
+          const int row = wr + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+          if (k < S.cand_cap) {
+            S.cd_t[k] = qt[row];
+            S.cd_c[k] = cslot;
+            S.cd_lb[k] = 0.0;
+          } else {
+            S.cnt->cand_overflow = 1;
           }
+          ++k;
         }
       }
     }
@@ -2215,6 +2352,390 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
   count_add(&S.cnt->visits[PASS == 0 ? 0 : 3], pairs);  // nonzero in thread 0 only
 }
 
+// ---- Gram search: interval screening of large candidate pairs -----------
+// A complete/average candidate whose exact value would cost many point
+// distances first gets a rigorous interval [L, H] from FP16 MFMA tiles over
+// its point pairs: the points are recentred and scaled once per call (psc),
+// rounded to FP16 with the same per-point terms as the centroids (|x~|^2, the
+// accumulation allowance e and the rounding norm eta). Per point pair with
+// s = sqrt(max(d2, 0)) and T = |x~ - y~|: |s - T| <= min(sqrt(E), E / s) for
+// E = e_x + e_y, and ||x - y| - T| <= eta_x + eta_y. Average sums s over the
+// tile; complete takes the largest d2. Each terminal's bound drops to its
+// smallest H, and only candidates with L <= bound are evaluated exactly.
+constexpr long long kIntervalWork = 16384;  // point pairs x d from which a pair is screened first
+constexpr int kIntervalMinDim = 32;         // below it exact FP64 tiles are cheaper than screening
+
+// per-dimension range of all points (once per call)
+__global__ void k_pt_range(const float *x, int n, int d, unsigned long long *gmin, unsigned long long *gmax) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, nw = (gridDim.x * blockDim.x) / kWave;
+  unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
+  for (int i = w0; i < n; i += nw)
+    for (int j = 0; j < 2; ++j) {
+      const int k = lane + j * kWave;
+      if (k < d) {
+        const unsigned long long b = ordered_bits((double)x[(size_t)i * d + k]);
+        lo[j] = b < lo[j] ? b : lo[j];
+        hi[j] = b > hi[j] ? b : hi[j];
+      }
+    }
+  for (int j = 0; j < 2; ++j) {
+    const int k = lane + j * kWave;
+    if (k < d && lo[j] != ~0ull) {
+      atomicMin(&gmin[k], lo[j]);
+      atomicMax(&gmax[k], hi[j]);
+    }
+  }
+}
+
+__global__ void k_pt_setup(State S) {
+  const int k = threadIdx.x;
+  __shared__ double rr[kGramMaxDim];
+  double r = 0.0;
+  if (k < S.d) {
+    const double lo = from_ordered_bits(S.gmin[k]), hi = from_ordered_bits(S.gmax[k]);
+    S.porg[k] = 0.5 * (lo + hi);
+    r = 0.5 * (hi - lo);
+  }
+  rr[k] = r;
+  __syncthreads();
+  if (k == 0) {
+    double m = 0.0;
+    for (int j = 0; j < S.d; ++j) m = rr[j] > m ? rr[j] : m;
+    *S.pscale = m > 0.0 ? 1.0 / m : 1.0;
+  }
+}
+
+// FP16 copy of every point in its current (permuted) place, and its FP32
+// terms: x = |x~|^2, y = e, z = eta (rounded up). A wave per point.
+__global__ void k_pt_prep(State S) {
+  const int n = S.n, d = S.d, kp = S.gkp;
+  const double sc = *S.pscale;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, nw = (gridDim.x * blockDim.x) / kWave;
+  for (int i = w0; i < n; i += nw) {
+    const float *p = S.px + (size_t)i * d;
+    double nrm = 0.0, err = 0.0;
+    for (int k = lane; k < kp; k += kWave) {
+      _Float16 h = (_Float16)0.0f;
+      if (k < d) {
+        const double xs = ((double)p[k] - S.porg[k]) * sc;
+        h = (_Float16)(float)xs;
+        const double hv = (double)(float)h;
+        nrm += hv * hv;
+        err += (xs - hv) * (xs - hv);
+      }
+      S.p16[(size_t)i * kp + k] = h;
+    }
+    nrm = wave_sum(nrm);
+    err = wave_sum(err);
+    if (lane == 0) {
+      const double e = 2.0 * (double)(kp + 8) * 5.9604644775390625e-8 * nrm + 1e-30;
+      const double eta = sqrt(err) * (1.0 + 1e-12) + 1e-15 * sqrt(nrm) + 1e-18;
+      S.pq[i] = make_float4((float)nrm, f32_up(e), f32_up(eta * (double)kGMargin), 0.0f);
+    }
+  }
+}
+
+// Candidates: small pairs (at most kInlinePairs point pairs) are listed for
+// an exact evaluation now, which also tightens the terminal's bound; large
+// pairs get their tile count and point ranges for the interval pass (the
+// cache is consulted only for the pairs that survive it). cd_lb < 0 marks a
+// candidate whose exact value is in cd_v.
+template <int LINK>
+__global__ void k_cand_triage(State S, int ncand) {
+  const int d = S.d;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncand; i += gridDim.x * blockDim.x) {
+    const int ti = S.cd_t[i], c = S.cd_c[i];
+    const int t = S.term[ti];
+    const int nt = S.csize[t], nc = S.csize[c];
+    const long long cost = (long long)nt * nc;
+    if (cost <= kInlinePairs) {
+      const long long k = append_slot(&S.cnt->n_small);
+      S.cd_small[k] = i;  // k < ncand: every candidate appends at most once
+    } else if (d >= kIntervalMinDim && cost * d >= kIntervalWork) {
+      // dense list of screened candidates: tile count, point ranges, index
+      const long long k = append_slot(&S.cnt->n_scr);
+      S.cd_tile0[k] = (long long)((nt + kGT - 1) / kGT) * ((nc + kGT - 1) / kGT);
+      S.cd_desc[k] = make_int4(S.cbeg[t], nt, S.cbeg[c], nc);
+      S.cd_scr[k] = i;
+      S.cd_lb[i] = 0.0;
+      S.cd_v[i] = 0.0;
+    }
+  }
+}
+
+__global__ void k_scr_count(Counters *c) { c->n_scr32 = (int)c->n_scr; }
+
+// Small candidates: a wavefront per candidate, a lane per point pair (rows:
+// the cluster with the lower ID), coordinates summed in order; points are
+// read in 16-byte pieces when d is a multiple of 4.
+template <int LINK>
+__global__ void k_cand_small(State S) {
+  const int nsm = (int)S.cnt->n_small, d = S.d;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, nw = (gridDim.x * blockDim.x) / kWave;
+  long long evals = 0, ppairs = 0;
+  for (int j = w0; j < nsm; j += nw) {
+    const int i = S.cd_small[j];
+    const int ti = S.cd_t[i], c = S.cd_c[i];
+    const int t = S.term[ti];
+    const bool tl = S.cid[t] < S.cid[c];
+    const int r = tl ? t : c, q = tl ? c : t;
+    const int nS = S.csize[q], cost = S.csize[r] * nS;
+    double val = 0.0;
+    if (lane < cost) {
+      const float *pr = S.px + (size_t)(S.cbeg[r] + lane / nS) * d;
+      const float *pc = S.px + (size_t)(S.cbeg[q] + lane % nS) * d;
+      double q2 = 0.0;
+      if ((d & 3) == 0) {
+        for (int k = 0; k < d; k += 4) {
+          const float4 a = *(const float4 *)(pr + k), b = *(const float4 *)(pc + k);
+          double u = (double)a.x - (double)b.x;
+          q2 += u * u;
+          u = (double)a.y - (double)b.y;
+          q2 += u * u;
+          u = (double)a.z - (double)b.z;
+          q2 += u * u;
+          u = (double)a.w - (double)b.w;
+          q2 += u * u;
+        }
+      } else {
+        for (int k = 0; k < d; ++k) {
+          const double u = (double)pr[k] - (double)pc[k];
+          q2 += u * u;
+        }
+      }
+      val = LINK == kComplete ? q2 : sqrt(q2);
+    }
+    val = LINK == kComplete ? wave_max(val) : wave_sum(val) / (double)cost;
+    if (lane == 0) {
+      S.cd_v[i] = val;
+      S.cd_lb[i] = -1.0;
+      atomicMin((unsigned long long *)&S.t_beta[ti], pos_bits(val));
+      ++evals;
+      ppairs += cost;
+    }
+  }
+  count_add(&S.cnt->cluster_evals, evals);
+  count_add(&S.cnt->point_pairs, ppairs);
+}
+
+// One block per 64x64 tile of a screened candidate's point pairs (rows: the
+// terminal's points), four 32x32 MFMA sub-tiles; the tile's bound
+// contributions are added (average) or maxed (complete) into the candidate.
+// Each block walks a contiguous range of tiles; the next tile's points are
+// loaded into registers while the current one is computed.
+template <int LINK, int KP>
+__global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
+  constexpr int CH = KP / 8;                           // 16-byte chunks per point
+  constexpr int NCH = (2 * kGT * CH + kBlock - 1) / kBlock;  // chunks per thread (both sides)
+  __shared__ __attribute__((aligned(16))) _Float16 sab[2][kGT][KP + 8];
+  __shared__ float an[2][kGT];
+  __shared__ float side[2][3];  // per side: sum eta, max eta, max e
+  __shared__ float red[3][kBlock / kWave];
+  const long long ntiles = S.cnt->n_ctiles;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const double isc = 1.0 / *S.pscale;
+  long long pairs = 0;
+  const int nscr = S.cnt->n_scr32;
+  long long ta, te;
+  tile_share(ntiles, ta, te);
+  if (ta >= te) {
+    count_add(&S.cnt->visits[1], 0);
+    return;
+  }
+  // the current screened entry and the next one (its metadata loaded one
+  // entry ahead); every entry has at least one tile
+  int own = tile_owner(S.cd_tile0, nscr, ta);
+  int4 ds = S.cd_desc[own];
+  int oi = S.cd_scr[own];
+  long long ostart = S.cd_tile0[own];
+  long long oend = own + 1 < nscr ? S.cd_tile0[own + 1] : ntiles;
+  int4 nds = make_int4(0, 0, 0, 0);
+  int ni = 0;
+  long long nend = ntiles;
+  auto ahead = [&]() {
+    if (own + 1 < nscr) {
+      nds = S.cd_desc[own + 1];
+      ni = S.cd_scr[own + 1];
+      nend = own + 2 < nscr ? S.cd_tile0[own + 2] : ntiles;
+    }
+  };
+  ahead();
+  uint4 reg[NCH];
+  float4 rq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  int cur_i = 0, cur_nr = 0, cur_nc = 0;
+  auto fetch = [&](long long tile) {
+    if (tile >= oend) {
+      ++own;
+      ostart = oend;
+      oend = nend;
+      ds = nds;
+      oi = ni;
+      ahead();
+    }
+    const long long local = tile - ostart;
+    const int ntc = (ds.w + kGT - 1) / kGT;
+    const int r0 = (int)(local / ntc) * kGT, c0 = (int)(local % ntc) * kGT;
+    const int nr = min(kGT, ds.y - r0), nc = min(kGT, ds.w - c0);
+    const int ba = ds.x + r0, bb = ds.z + c0;
+#pragma unroll
+    for (int u = 0; u < NCH; ++u) {
+      const int j = threadIdx.x + u * kBlock;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (j < 2 * kGT * CH) {
+        const int sd = j / (kGT * CH), r = (j / CH) % kGT, c8 = j % CH;
+        if (r < (sd ? nc : nr)) v = *(const uint4 *)(S.p16 + (size_t)((sd ? bb : ba) + r) * KP + c8 * 8);
+      }
+      reg[u] = v;
+    }
+    rq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (w < 2 && lane < (w ? nc : nr)) rq = S.pq[(w ? bb : ba) + lane];
+    cur_i = oi;
+    cur_nr = nr;
+    cur_nc = nc;
+  };
+  fetch(ta);
+  for (long long tile = ta; tile < te; ++tile) {
+    const int i = cur_i, nr = cur_nr, ncl = cur_nc;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NCH; ++u) {
+      const int j = threadIdx.x + u * kBlock;
+      if (j < 2 * kGT * CH) {
+        const int sd = j / (kGT * CH), r = (j / CH) % kGT, c8 = j % CH;
+        *(uint4 *)&sab[sd][r][c8 * 8] = reg[u];
+      }
+    }
+    if (w < 2) {
+      an[w][lane] = rq.x;
+      float se = rq.z, me = rq.z, mx = rq.y;
+      for (int o = kWave / 2; o > 0; o >>= 1) {
+        se += __shfl_xor(se, o, kWave);
+        me = fmaxf(me, __shfl_xor(me, o, kWave));
+        mx = fmaxf(mx, __shfl_xor(mx, o, kWave));
+      }
+      if (lane == 0) {
+        side[w][0] = se;
+        side[w][1] = me;
+        side[w][2] = mx;
+      }
+    }
+    __syncthreads();
+    if (tile + 1 < te) fetch(tile + 1);  // in flight during the tile's arithmetic
+    float16v acc = {};
+#pragma unroll
+    for (int kk = 0; kk < KP; kk += 16) {
+      const half8 a = *(const half8 *)&sab[0][wr + (lane & 31)][kk + (lane >> 5) * 8];
+      const half8 b = *(const half8 *)&sab[1][wc + (lane & 31)][kk + (lane >> 5) * 8];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
+    }
+    const int col = wc + (lane & 31);
+    const bool cval = col < ncl;
+    const float cn = an[1][col];
+    // accumulation allowance of the tile (rounded up), and its root
+    const float Ef = (side[0][2] + side[1][2]) * kGMargin;
+    const float rE = __builtin_amdgcn_sqrtf(Ef) * kGMargin;
+    float sum = 0.0f, smin = INFINITY, mx = -INFINITY;
+    int cnt = 16;
+    if (nr == kGT && ncl == kGT) {
+      // full tile: no masks
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int row = wr + (k >> 2) * 8 + (lane >> 5) * 4 + (k & 3);
+        const float d2 = __builtin_fmaf(-2.0f, acc[k], an[0][row] + cn);
+        if (LINK == kAverage) {
+          const float s = __builtin_amdgcn_sqrtf(fmaxf(d2, 0.0f));
+          sum += s;
+          smin = fminf(smin, s);
+        } else {
+          mx = fmaxf(mx, d2);
+        }
+      }
+    } else {
+      cnt = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int row = wr + (k >> 2) * 8 + (lane >> 5) * 4 + (k & 3);
+        const bool v = cval && row < nr;
+        const float d2 = __builtin_fmaf(-2.0f, acc[k], an[0][row] + cn);
+        if (LINK == kAverage) {
+          const float s = __builtin_amdgcn_sqrtf(fmaxf(d2, 0.0f));
+          sum += v ? s : 0.0f;
+          smin = fminf(smin, v ? s : INFINITY);
+          cnt += v ? 1 : 0;
+        } else {
+          mx = fmaxf(mx, v ? d2 : -INFINITY);
+        }
+      }
+    }
+    // every pair of this lane: |s - T| <= min(sqrt(E), E / s) <= min(sqrt(E), E / smin)
+    float eps = 0.0f;
+    if (LINK == kAverage)
+      eps = (float)cnt * fminf(rE, Ef * __builtin_amdgcn_rcpf(smin) * kGMargin) * kGMargin;
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      sum += __shfl_xor(sum, o, kWave);
+      eps += __shfl_xor(eps, o, kWave);
+      mx = fmaxf(mx, __shfl_xor(mx, o, kWave));
+    }
+    if (lane == 0) {
+      red[0][w] = sum;
+      red[1][w] = eps;
+      red[2][w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0, ep = 0.0, m = -INFINITY;
+      for (int j = 0; j < kBlock / kWave; ++j) {
+        s += (double)red[0][j];
+        ep += (double)red[1][j];
+        m = fmax(m, (double)red[2][j]);
+      }
+      const double E = (double)side[0][2] + (double)side[1][2];
+      pairs += (long long)nr * ncl;
+      if (LINK == kAverage) {
+        // FP32 sums of at most 16 + 6 terms per partial: relative 4e-6 covers them
+        const double err = (double)ncl * side[0][0] + (double)nr * side[1][0] + ep * (1.0 + 4e-6) + s * 4e-6;
+        const double l = s - err > 0.0 ? s - err : 0.0;
+        atomicAdd(&S.cd_lb[i], l * isc);
+        atomicAdd(&S.cd_v[i], (s + err) * isc);
+      } else {
+        const double em = (double)side[0][1] + (double)side[1][1];
+        const double tl = sqrt(m - E > 0.0 ? m - E : 0.0) * (1.0 - 1e-6) - em;
+        const double th = sqrt(m + E > 0.0 ? m + E : 0.0) * (1.0 + 1e-6) + em;
+        const double kl = tl > 0.0 ? tl * tl * isc * isc : 0.0;
+        atomicMax((unsigned long long *)&S.cd_lb[i], pos_bits(kl));
+        atomicMax((unsigned long long *)&S.cd_v[i], pos_bits(th * th * isc * isc));
+      }
+    }
+  }
+  count_add(&S.cnt->visits[1], pairs);  // nonzero in thread 0 only
+}
+
+// Screened candidates: L kept as the candidate's lower bound, H lowers the
+// terminal's bound.
+template <int LINK>
+__global__ void k_cand_bound(State S) {
+  const int nscr = S.cnt->n_scr32;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nscr; k += gridDim.x * blockDim.x) {
+    const int i = S.cd_scr[k];
+    const int ti = S.cd_t[i], c = S.cd_c[i];
+    double l = S.cd_lb[i], h = S.cd_v[i];
+    if (LINK == kAverage) {
+      const double np = (double)S.csize[S.term[ti]] * (double)S.csize[c];
+      l = l / np * (1.0 - 1e-12);
+      h = h / np * (1.0 + 1e-12);
+    } else {
+      l *= 1.0 - 1e-12;
+      h *= 1.0 + 1e-12;
+    }
+    S.cd_lb[i] = l;
+    atomicMin((unsigned long long *)&S.t_beta[ti], pos_bits(h));
+  }
+}
+
 // Recorded candidates: exact FP64 value (Ward, small complete/average pairs,
 // cache hits) or a claim on the pair for the tile pass.
 template <int LINK>
@@ -2224,8 +2745,14 @@ __global__ void k_gram_exact(State S) {
   long long evals = 0, ppairs = 0, hits = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
     const int ti = S.cd_t[i], c = S.cd_c[i];
+    const double lb = S.cd_lb[i];
+    if (LINK != kWard && lb < 0.0) {
+      // exact value of a small pair, from the triage pass
+      atomicMin(&S.t_min[ti], pos_bits(S.cd_v[i]));
+      continue;
+    }
     S.cd_v[i] = NAN;
-    if (S.cd_lb[i] > S.t_beta[ti] * kSlack) continue;
+    if (lb > S.t_beta[ti] * kSlack) continue;
     const int t = S.term[ti];
     double v;
     if (LINK == kWard) {
@@ -2591,6 +3118,38 @@ void launch_gram_kp(State &S, int nact, hipStream_t s) {
   tmark(S, 0, true, s);
   tmark(S, 3, false, s);
   k_gram<LINK, KP, 1><<<dim3(gx, gy), kBlock, 0, s>>>(S);
+  tmark(S, 3, true, s);
+}
+
+template <int LINK, int KP>
+void launch_cand_tiles(State &S, int ncand, hipStream_t s) {
+  k_cand_tiles<LINK, KP><<<8192, kBlock, 0, s>>>(S, ncand);
+}
+
+// Candidates of a batch: interval screening (complete/average), then exact
+// values or claims.
+template <int LINK>
+void launch_gram_refine_t(State &S, int ncand, hipStream_t s) {
+  if constexpr (LINK != kWard) {
+    if (!S.p16 || ncand <= 0) goto exact;
+    tmark(S, 1, false, s);
+    k_cand_triage<LINK><<<nblk(ncand, 4096), kBlock, 0, s>>>(S, ncand);
+    k_cand_small<LINK><<<8192, kBlock, 0, s>>>(S);
+    k_scr_count<<<1, 1, 0, s>>>(S.cnt);
+    scan_exclusive_i64(S.cd_tile0, S.cd_tile0, ncand, &S.cnt->n_scr32, &S.cnt->n_ctiles, S.part, s);
+    switch (S.gkp) {
+    case 16: launch_cand_tiles<LINK, 16>(S, ncand, s); break;
+    case 32: launch_cand_tiles<LINK, 32>(S, ncand, s); break;
+    case 64: launch_cand_tiles<LINK, 64>(S, ncand, s); break;
+    case 80: launch_cand_tiles<LINK, 80>(S, ncand, s); break;
+    case 128: launch_cand_tiles<LINK, 128>(S, ncand, s); break;
+    default: launch_cand_tiles<LINK, 144>(S, ncand, s); break;
+    }
+    k_cand_bound<LINK><<<nblk(ncand, 4096), kBlock, 0, s>>>(S);
+    tmark(S, 1, true, s);
+  }
+exact:
+  tmark(S, 3, false, s);
   k_gram_exact<LINK><<<2048, kBlock, 0, s>>>(S);
   tmark(S, 3, true, s);
 }
@@ -2601,6 +3160,7 @@ void launch_gram_setup(State &S, int nact, hipStream_t s) {
   k_gram_range<<<nblk((long long)nact * kWave, 1024), kBlock, 0, s>>>(S);
   k_gram_setup<<<1, kGramMaxDim, 0, s>>>(S);
   k_gram_prep<<<nblk((long long)nact * kWave, 4096), kBlock, 0, s>>>(S);
+  if (S.p16) k_pt_prep<<<nblk((long long)S.n * kWave, 4096), kBlock, 0, s>>>(S);
 }
 
 template <int LINK>
@@ -2620,6 +3180,14 @@ void launch_gram_batch_t(State &S, int nact, hipStream_t s) {
 }  // namespace
 
 void launch_gram_keys(State &S, hipStream_t s) { k_gram_key<<<2048, kBlock, 0, s>>>(S); }
+
+void launch_gram_refine(State &S, int ncand, hipStream_t s) {
+  switch (S.linkage) {
+  case kWard: launch_gram_refine_t<kWard>(S, ncand, s); break;
+  case kComplete: launch_gram_refine_t<kComplete>(S, ncand, s); break;
+  default: launch_gram_refine_t<kAverage>(S, ncand, s); break;
+  }
+}
 
 void launch_gram_batch(State &S, int nact, hipStream_t s) {
   switch (S.linkage) {
@@ -2667,6 +3235,12 @@ void launch_init(State &S, const float *x, hipStream_t s) {
   radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, n, axes == 2 ? 32 : 16, S.hist, S.part, s);
   k_init_slots<<<nblk(n, 1 << 22), kBlock, 0, s>>>(S, x, S.sv0);
   k_set_nact<<<1, 1, 0, s>>>(S.cnt, n);
+  if (S.p16) {
+    // point scaling of the interval tiles, fixed for the call
+    k_gram_reset<<<1, kGramMaxDim, 0, s>>>(S);
+    k_pt_range<<<nblk((long long)n * kWave, 1024), kBlock, 0, s>>>(x, n, S.d, S.gmin, S.gmax);
+    k_pt_setup<<<1, kGramMaxDim, 0, s>>>(S);
+  }
 }
 
 // First half of a round: terminals, grid, nearest-neighbour search (Ward
@@ -2747,6 +3321,7 @@ void launch_pairs(State &S, int round, int npairs, long long work, hipStream_t s
       if (S.d <= 2) k_tiles_comp<2><<<2048, kBlock, 0, s>>>(S);
       else if (S.d <= 4) k_tiles_comp<4><<<2048, kBlock, 0, s>>>(S);
       else if (S.d <= 16) k_tiles_comp<16><<<2048, kBlock, 0, s>>>(S);
+      else if (S.d <= kGramMaxDim) k_tiles_hd<kComplete><<<4096, kBlock, 0, s>>>(S);
       else k_tiles_comp<0><<<2048, kBlock, 0, s>>>(S);
       tmark(S, 2, true, s);
     } else {
@@ -2756,6 +3331,7 @@ void launch_pairs(State &S, int round, int npairs, long long work, hipStream_t s
       if (S.d <= 2) k_tiles_avg<2><<<tb, kBlock, 0, s>>>(S, ntiles);
       else if (S.d <= 4) k_tiles_avg<4><<<tb, kBlock, 0, s>>>(S, ntiles);
       else if (S.d <= 16) k_tiles_avg<16><<<tb, kBlock, 0, s>>>(S, ntiles);
+      else if (S.d <= kGramMaxDim) k_tiles_hd<kAverage><<<(int)std::min<long long>(ntiles, 8192), kBlock, 0, s>>>(S);
       else k_tiles_avg<0><<<tb, kBlock, 0, s>>>(S, ntiles);
       tmark(S, 2, true, s);
     }

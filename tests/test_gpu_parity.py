@@ -243,3 +243,21 @@ def test_gram_batches(pc, link, monkeypatch):
     assert same_rows(Z0, Z1, link) and same_rows(Z0, Z2, link)
     Zo, _ = oracle.nnchain(x, link, threads=8)
     assert _trees.same_tree(Z0, Zo, 2500, rtol=RTOL[link])
+
+
+@pytest.mark.parametrize("link", ["complete", "average"])
+@pytest.mark.parametrize("d", [40, 64, 128])
+def test_interval_screening(pc, link, d):
+    """Large candidate pairs (d >= 32) are first bracketed by FP16 MFMA point
+    tiles with rigorous FP32 error terms; only pairs whose lower end reaches
+    the bound are evaluated exactly. The rows must still match the oracle."""
+    n = 2000
+    x = synth.sphere_blobs(n, d, 12, 0.1, 60 + d)
+    Zo, cert = oracle.nnchain(x, link, threads=8)
+    if cert["min_gap"] < 1e-10:
+        pytest.skip("input not certified tie-free")
+    Zg, st = pc.hac(x, link, return_stats=True)
+    assert st["kernels"]["block_search"]["visits"] > 0  # point pairs screened
+    assert _trees.same_tree(Zg, Zo, n, rtol=RTOL[link])
+    Z0 = pc.hac(x, link, cache_slots=0)
+    assert same_rows(Zg, Z0, link)
