@@ -46,6 +46,81 @@ KERNEL_NAMES = ("ring_search", "block_search", "pair_tiles", "ring_emit")
 LINKS = ("ward", "complete")
 
 
+def serve_bench(num, slots, n_max):
+    """Serving leg: a Poisson trace of clustering requests of uneven n, d and
+    linkage (the serving law of ``synth.serving_trace``), first solved one at
+    a time on one context, then submitted at their arrival times to a server
+    with ``slots`` slots (open loop; the arrival rate makes the trace arrive in
+    80% of the one-at-a-time solve time, an offered load 1.25x what
+    one-at-a-time solving sustains; latency = completion - arrival, p50/p99),
+    then all at once (closed loop: throughput against one at a time)."""
+    import numpy as np
+
+    import paper_2106_04727_amd as pc
+    import synth
+
+    trace = synth.serving_trace(num, 1.0, seed=41, n_max=n_max)
+    xs = [synth.request_points(r) for r in trace]
+    ctx = pc.Context(0)
+    outs = [np.zeros((max(r["n"] - 1, 1), 4), np.int64) for r in trace]
+    # warm the device code paths once on small requests of each shape class
+    for d in (2, 3, 10, 64):
+        for link in ("complete", "average", "ward"):
+            w = synth.blobs(300, d, 5, 0.02, 7)
+            o = np.zeros((299, 4), np.int64)
+            ctx.hac(w.ctypes.data, 300, d, link, o.ctypes.data, points_on_device=False, out_on_device=False)
+    t0 = time.perf_counter()
+    for r, x, o in zip(trace, xs, outs):
+        ctx.hac(x.ctypes.data, r["n"], r["d"], r["linkage"], o.ctypes.data, points_on_device=False,
+                out_on_device=False)
+    t_seq = time.perf_counter() - t0
+    ctx.close()
+    span = 0.8 * t_seq
+    scale = span / max(trace[-1]["t"], 1e-9)
+    arrivals = [r["t"] * scale for r in trace]
+    lat = []
+    with pc.Server(device=0, slots=slots) as srv:
+        start = time.perf_counter()
+        tickets = []
+        for a, r, x in zip(arrivals, trace, xs):
+            dt = a - (time.perf_counter() - start)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append((srv.submit(x, r["linkage"]), time.perf_counter() - start))
+        for t, at in tickets:
+            info = srv.wait(t)
+            if info["status"] != 0:
+                raise RuntimeError("request failed: %s" % info["error"])
+            lat.append(info["t_done_ms"] - info["t_submit_ms"])
+            srv.release(t)
+        makespan = time.perf_counter() - start
+        st = srv.stats()
+        # closed loop: the whole trace submitted at once (throughput against
+        # one-at-a-time solving of the same requests)
+        start = time.perf_counter()
+        burst = [srv.submit(x, r["linkage"]) for r, x in zip(trace, xs)]
+        for t in burst:
+            info = srv.wait(t)
+            if info["status"] != 0:
+                raise RuntimeError("request failed: %s" % info["error"])
+            srv.release(t)
+        burst_s = time.perf_counter() - start
+    return {
+        "requests": num, "slots": slots, "n_max": n_max,
+        "trace": "Poisson arrivals; n log-uniform [256, n_max], d uniform {2,3,10,64}, linkage uniform "
+                 "{complete, average, ward}, 5-100 Gaussian blobs, sigma 0.01-0.05 (seed 41)",
+        "one_at_a_time_s": t_seq, "one_at_a_time_req_per_s": num / t_seq,
+        "offered_rate_req_per_s": num / span,
+        "open_loop_makespan_s": makespan,
+        "burst_makespan_s": burst_s, "burst_req_per_s": num / burst_s,
+        "burst_speedup_vs_one_at_a_time": t_seq / burst_s,
+        "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+        "latency_ms_max": float(np.max(lat)),
+        "peak_running": st["peak_running"], "peak_bytes_in_use": st["peak_bytes_in_use"],
+        "budget_bytes": st["budget_bytes"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +130,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the 10M Ward run")
     ap.add_argument("--links", default=",".join(LINKS))
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests of the serving trace (0 skips the serving leg)")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-nmax", type=int, default=200_000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -176,6 +255,12 @@ def main():
             del x10t
         except Exception as e:  # reported, never hidden
             out["ward_10m"] = {"error": str(e)}
+
+    if args.serve_requests > 0:
+        try:
+            out["serving"] = serve_bench(args.serve_requests, args.serve_slots, args.serve_nmax)
+        except Exception as e:  # reported, never hidden
+            out["serving"] = {"error": str(e)}
 
     if not args.no_cpu:
         import oracle

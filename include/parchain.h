@@ -138,6 +138,84 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
                  int32_t linkage, const pc_options *opt, pc_merge *out, int out_on_device,
                  void *stream, pc_stats *stats);
 
+/*
+ * ---- Serving: many requests on one device --------------------------------
+ * A server keeps up to `slots` requests on the GPU at once, each on its own
+ * context and HIP stream, so the rounds of different requests overlap on the
+ * device; requests that arrive while others run are admitted as slots and
+ * memory free up (continuous batching of whole requests). Admission: a
+ * request's device footprint is pc_hac_workspace_bytes(n, d, linkage, opt)
+ * (the initial workspace; record buffers can grow beyond it during a run),
+ * and a request starts when a slot is free and its footprint fits in the
+ * budget left by the running ones. Waiting requests are taken in arrival
+ * order; a later request that fits may start before an earlier one that does
+ * not (first fit), until the earlier one has been passed over 16 times.
+ * A request whose footprint exceeds the whole budget is refused at submission
+ * with PC_ERR_OUT_OF_MEMORY. A request's rows are those pc_hac computes for
+ * the same input, whatever else runs. All server functions are thread-safe.
+ */
+typedef struct pc_server pc_server;
+
+typedef struct {
+    uint32_t struct_size;       /* sizeof(pc_server_options) */
+    int32_t slots;              /* requests on the device at once, 1..64; <= 0 selects 4 */
+    uint64_t hbm_budget_bytes;  /* admission budget; 0 selects 80% of the device's free memory */
+    double fake_us_per_kpoint;  /* test hook: > 0 runs no device work at all; a request then
+                                   occupies its slot for this many microseconds per 1000
+                                   points and its rows are zero (host-only tests of admission) */
+} pc_server_options;
+
+typedef struct {
+    uint32_t struct_size;     /* sizeof(pc_request_info), set by the caller */
+    int32_t status;           /* pc_status of the request (PC_ERR_CANCELLED if cancelled) */
+    int32_t state;            /* 0 waiting, 1 running, 2 done, 3 cancelled */
+    int32_t slot;             /* slot that ran it, -1 before */
+    uint64_t footprint_bytes; /* admission footprint */
+    double t_submit_ms, t_start_ms, t_done_ms; /* server clock: ms since pc_server_create */
+    pc_stats stats;           /* pc_hac's counters for the request (struct_size set) */
+    char error[120];          /* pc_last_error() text of a failed request */
+} pc_request_info;
+
+typedef struct {
+    uint32_t struct_size;     /* sizeof(pc_server_stats), set by the caller */
+    int32_t slots;
+    int64_t submitted, completed, rejected, cancelled, failed;
+    int32_t running, queued, peak_running, reserved;
+    uint64_t budget_bytes, bytes_in_use, peak_bytes_in_use;
+} pc_server_stats;
+
+/* Create a server on HIP device `device` (current device if < 0); opt may be
+ * NULL. Each slot holds a context and a non-blocking stream of its own. */
+pc_status pc_server_create(int device, const pc_server_options *opt, pc_server **out);
+
+/* Queue a request. `points` (host, float32, n x d row-major) and `out` (host,
+ * n-1 rows) stay owned by the caller and must stay valid until the request
+ * is done or cancelled; the server reads and writes them from its worker
+ * threads. *ticket identifies the request. Bad arguments give
+ * PC_ERR_INVALID_ARG; a footprint above the budget PC_ERR_OUT_OF_MEMORY;
+ * non-finite coordinates are reported as the request's status. */
+pc_status pc_server_submit(pc_server *srv, const float *points, int64_t n, int32_t d, int32_t linkage,
+                           const pc_options *opt, pc_merge *out, uint64_t *ticket);
+
+/* State of a request (info may be NULL). Unknown tickets: PC_ERR_INVALID_ARG. */
+pc_status pc_server_poll(pc_server *srv, uint64_t ticket, pc_request_info *info);
+
+/* Wait until the request is done or cancelled; timeout_ms < 0 waits without
+ * limit. PC_ERR_BUSY when the time runs out (info then shows the state). */
+pc_status pc_server_wait(pc_server *srv, uint64_t ticket, double timeout_ms, pc_request_info *info);
+
+/* Cancel a waiting request (its status becomes PC_ERR_CANCELLED). A running
+ * request cannot be cancelled: PC_ERR_BUSY. Finished requests: no effect. */
+pc_status pc_server_cancel(pc_server *srv, uint64_t ticket);
+
+/* Forget a finished or cancelled request (its ticket becomes unknown). */
+pc_status pc_server_release(pc_server *srv, uint64_t ticket);
+
+pc_status pc_server_get_stats(pc_server *srv, pc_server_stats *stats);
+
+/* Cancel every waiting request, let the running ones finish, free all. */
+void pc_server_destroy(pc_server *srv);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *pc_last_error(void);
 

@@ -7,6 +7,7 @@ from .parchain import (  # noqa: F401
     LINKAGES,
     PCError,
     Context,
+    Server,
     hac,
     hac_device,
     load_library,

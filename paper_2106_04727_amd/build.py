@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libparchain.so")
-SOURCES = ["pc_prims.hip", "pc_round.hip", "pc_api.hip"]
+SOURCES = ["pc_prims.hip", "pc_round.hip", "pc_api.hip", "pc_server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -197,6 +197,30 @@ pc_status pc_context_create(int device, pc_context **out) {
   return PC_OK;
 }
 
+}  // extern "C"
+
+namespace pc {
+void set_error(const char *msg) { g_err = msg; }
+
+// Device bytes a context holds, and release of its growable buffers (the
+// serving layer keeps each slot within its share of the budget).
+size_t context_bytes(const pc_context *c) {
+  size_t b = c->ws.bytes + c->pairs.bytes + c->tiles.bytes + c->part.bytes + c->fidx.bytes + c->cand.bytes;
+  return b + c->cache[0].bytes + c->cache[1].bytes;
+}
+
+void context_trim(pc_context *c) {
+  hipSetDevice(c->device);
+  for (Buf *b : {&c->ws, &c->pairs, &c->tiles, &c->part, &c->fidx, &c->cand, &c->cache[0], &c->cache[1]}) {
+    if (b->p) hipFree(b->p);
+    b->p = nullptr;
+    b->bytes = 0;
+  }
+}
+}  // namespace pc
+
+extern "C" {
+
 void pc_context_destroy(pc_context *c) {
   if (!c) return;
   hipSetDevice(c->device);
@@ -218,14 +242,20 @@ void pc_context_destroy(pc_context *c) {
 }
 
 size_t pc_hac_workspace_bytes(int64_t n, int32_t d, int32_t linkage, const pc_options *opt) {
-  (void)opt;
   if (n < 1 || d < 1 || d > kMaxDim || n > 2147483646LL || linkage < 0 || linkage > 2) return 0;
   State S;
   size_t bytes = layout(S, nullptr, n, d, linkage, true);
+  const bool gram = d >= kGramMinDim && d <= kGramMaxDim;
+  // initial candidate record (grown on demand), pair list, tiles and filter
+  const size_t cand = (size_t)std::max<int64_t>(1 << 22, 4 * n);
+  const size_t per_cand = 2 * sizeof(double) + sizeof(long long) + sizeof(int4) + 4 * sizeof(int);
+  if (linkage != kWard || gram) bytes += cand * per_cand + 1024;
+  bytes += ((size_t)(2 * n + 64) / 1024 + 1024) * sizeof(long long);
   if (linkage != kWard) {
     const size_t pc = (size_t)std::max<int64_t>(1 << 20, 2 * n);
-    bytes += pc * (3 * sizeof(long long) + 6 * sizeof(int)) + 1024;
+    bytes += pc * (4 * sizeof(long long) + 6 * sizeof(int)) + 1024;
     if (linkage == kAverage) bytes += ((size_t)1 << 22) * sizeof(double);
+    if (linkage == kComplete) bytes += cand * sizeof(int);
     int cs = opt ? opt->cache_slots : -1;
     if (cs < 0) cs = linkage == kAverage ? 64 : 0;
     if (cs > 0) {

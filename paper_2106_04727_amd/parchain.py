@@ -73,8 +73,44 @@ class pc_stats(ctypes.Structure):
 _lib = None
 _lock = threading.Lock()
 
+class pc_server_options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("slots", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("fake_us_per_kpoint", ctypes.c_double)]
+
+
+class pc_request_info(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("status", ctypes.c_int32),
+                ("state", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("footprint_bytes", ctypes.c_uint64), ("t_submit_ms", ctypes.c_double),
+                ("t_start_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
+                ("stats", pc_stats), ("error", ctypes.c_char * 120)]
+
+    STATES = ("waiting", "running", "done", "cancelled")
+
+    def as_dict(self):
+        return {"status": self.status, "state": self.STATES[self.state], "slot": self.slot,
+                "footprint_bytes": self.footprint_bytes, "t_submit_ms": self.t_submit_ms,
+                "t_start_ms": self.t_start_ms, "t_done_ms": self.t_done_ms,
+                "stats": self.stats.as_dict(), "error": self.error.decode(errors="replace")}
+
+
+class pc_server_stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("slots", ctypes.c_int32),
+                ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("running", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("peak_running", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("budget_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
+                ("peak_bytes_in_use", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("struct_size", "reserved")}
+
+
 EXPORTS = ["pc_context_create", "pc_context_destroy", "pc_hac_workspace_bytes", "pc_hac",
-           "pc_last_error", "pc_version"]
+           "pc_last_error", "pc_version", "pc_server_create", "pc_server_submit", "pc_server_poll",
+           "pc_server_wait", "pc_server_cancel", "pc_server_release", "pc_server_get_stats",
+           "pc_server_destroy"]
 
 
 def load_library(path: str | None = None):
@@ -101,6 +137,23 @@ def load_library(path: str | None = None):
         lib.pc_last_error.restype = ctypes.c_char_p
         lib.pc_version.argtypes = []
         lib.pc_version.restype = ctypes.c_char_p
+        lib.pc_server_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
+        lib.pc_server_create.restype = ctypes.c_int
+        lib.pc_server_submit.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                         ctypes.POINTER(ctypes.c_uint64)]
+        lib.pc_server_submit.restype = ctypes.c_int
+        lib.pc_server_poll.argtypes = [vp, ctypes.c_uint64, vp]
+        lib.pc_server_poll.restype = ctypes.c_int
+        lib.pc_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, vp]
+        lib.pc_server_wait.restype = ctypes.c_int
+        lib.pc_server_cancel.argtypes = [vp, ctypes.c_uint64]
+        lib.pc_server_cancel.restype = ctypes.c_int
+        lib.pc_server_release.argtypes = [vp, ctypes.c_uint64]
+        lib.pc_server_release.restype = ctypes.c_int
+        lib.pc_server_get_stats.argtypes = [vp, vp]
+        lib.pc_server_get_stats.restype = ctypes.c_int
+        lib.pc_server_destroy.argtypes = [vp]
+        lib.pc_server_destroy.restype = None
         if path is None:
             _lib = lib
         return lib
@@ -223,3 +276,89 @@ def hac(x, linkage, *, prune: bool = True, device: int = 0, return_stats: bool =
     torch.cuda.synchronize(xt.device)
     Z = rows_to_Z(rows)
     return (Z, st) if return_stats else Z
+
+
+class Server:
+    """A pc_server: many clustering requests on one device (see parchain.h).
+
+    ``submit`` copies nothing: the point array and the output rows are kept
+    alive here until the request is released.
+    """
+
+    def __init__(self, device: int = 0, slots: int = 4, hbm_budget_bytes: int = 0,
+                 fake_us_per_kpoint: float = 0.0):
+        self.lib = load_library()
+        opt = pc_server_options(ctypes.sizeof(pc_server_options), int(slots), int(hbm_budget_bytes),
+                                float(fake_us_per_kpoint))
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.pc_server_create(int(device), ctypes.byref(opt), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, x, linkage, *, cache_slots: int = -1, prune: bool = True) -> int:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        n, d = x.shape
+        out = np.zeros((max(n - 1, 1), 4), np.int64)
+        opt = pc_options(ctypes.sizeof(pc_options), 0, 1 if prune else 0, 0, int(cache_slots), 0)
+        t = ctypes.c_uint64()
+        _check(self.lib, self.lib.pc_server_submit(self.handle, x.ctypes.data, n, d, _link(linkage),
+                                                   ctypes.byref(opt), out.ctypes.data, ctypes.byref(t)))
+        self._keep[t.value] = (x, out, n)
+        return t.value
+
+    def _info(self):
+        info = pc_request_info()
+        info.struct_size = ctypes.sizeof(pc_request_info)
+        return info
+
+    def poll(self, ticket: int) -> dict:
+        info = self._info()
+        _check(self.lib, self.lib.pc_server_poll(self.handle, ticket, ctypes.byref(info)))
+        return info.as_dict()
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0) -> dict:
+        info = self._info()
+        _check(self.lib, self.lib.pc_server_wait(self.handle, ticket, float(timeout_ms), ctypes.byref(info)))
+        return info.as_dict()
+
+    def result(self, ticket: int, release: bool = True):
+        """Wait for the request; return (Z, info); raise PCError if it failed."""
+        info = self.wait(ticket)
+        if info["status"] != PC_OK:
+            raise PCError(info["status"], info["error"])
+        _, out, n = self._keep[ticket]
+        Z = rows_to_Z(out[: n - 1])
+        if release:
+            self.release(ticket)
+        return Z, info
+
+    def cancel(self, ticket: int):
+        _check(self.lib, self.lib.pc_server_cancel(self.handle, ticket))
+
+    def release(self, ticket: int):
+        _check(self.lib, self.lib.pc_server_release(self.handle, ticket))
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = pc_server_stats()
+        st.struct_size = ctypes.sizeof(pc_server_stats)
+        _check(self.lib, self.lib.pc_server_get_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pc_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
