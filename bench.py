@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_VEC_TFLOPS = 78.6
+PEAK_FP16_MFMA_TFLOPS = 2500.0
 
 # Algorithmic unit costs.
 #   search kernels: per candidate visited, its 16-byte (slot, size, cid) record
@@ -44,6 +45,69 @@ COMPLETE_PAIR_FLOPS = 6
 KERNEL_NAMES = ("ring_search", "block_search", "pair_tiles", "ring_emit")
 
 LINKS = ("ward", "complete")
+
+
+def gram_kp(d):
+    """MFMA depth of the Gram tiles for dimension d (d plus two augmented
+    coordinates, in steps of 16)."""
+    for kp in (16, 32, 64, 80, 128):
+        if d + 2 <= kp:
+            return kp
+    return 144
+
+
+def roofline(kname, link, d, ms, nl, sts):
+    """Roofline entry of the step's dominant kernel: algorithmic work per
+    launch (unit cost x units counted by the library) / average launch time
+    (HIP events on the library's stream), against MI355X's published peak."""
+    avg_ms = ms / nl
+    gram = 4 <= d <= 128
+    visits = sum(s["kernels"][kname]["visits"] for s in sts)
+    if kname == "pair_tiles":
+        # exact tiles: FP64 flops per point pair (d sub, d mul, d add, + max or sqrt/add)
+        flops = COMPLETE_PAIR_FLOPS if d == 2 else 3 * d + 1
+        work = sum(s["point_pair_evals"] for s in sts) * flops / nl
+        achieved = work / (avg_ms / 1000.0) / 1e12
+        r = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VEC_TFLOPS, "unit": "TFLOP/s",
+             "note": "exact FP64 point-pair tiles; work = point pairs x FP64 flops per pair"}
+    elif gram and kname in ("ring_search", "ring_emit", "block_search"):
+        # Gram passes (centroid pairs) and interval tiles (point pairs): FP16 MFMA,
+        # 2 x K flops per pair
+        work = visits * 2 * gram_kp(d) / nl
+        achieved = work / (avg_ms / 1000.0) / 1e12
+        r = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
+             "note": "FP16 MFMA tiles; work = pairs x 2K flops (K = %d)" % gram_kp(d)}
+    else:
+        work = visits * visit_bytes(link, d) / nl
+        achieved = work / (avg_ms / 1000.0) / 1e9
+        r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+             "note": "search kernels gather candidate records; work = visits x record bytes"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = measured_traffic(kname, link, d)
+    r.update({"kernel": kname, "linkage": link, "avg_launch_ms": avg_ms, "launches": nl,
+              "work_per_launch": work})
+    return r
+
+
+def measured_traffic(kname, link, d):
+    """HBM bytes per launch of the kernel from the committed rocprofv3 PMC
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None when there is none or the kernel source changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "blob50_1m_d2_%s_%s_traffic.md" % (link, kname))
+    if d != 2 or not os.path.exists(path):
+        return None
+    src = os.path.join(ROOT, "paper_2106_04727_amd", "csrc", "pc_round.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != sha:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
 
 
 def serve_bench(num, slots, n_max):
@@ -134,6 +198,10 @@ def main():
                     help="requests of the serving trace (0 skips the serving leg)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-nmax", type=int, default=200_000)
+    ap.add_argument("--workload", default="blob50_1m_d2",
+                    help="named input of synth.WORKLOADS (the headline is blob50_1m_d2)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy 256 MiB on the device first (calibrates HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -149,11 +217,20 @@ def main():
     import synth
 
     links = [l for l in args.links.split(",") if l]
-    n = args.n
-    x = synth.blobs(n, 2, 50, 0.01, 11)
+    if args.workload == "blob50_1m_d2":
+        x = synth.blobs(args.n, 2, 50, 0.01, 11)
+    else:
+        x = synth.WORKLOADS[args.workload]()
+    n, d = x.shape
     dev = torch.device("cuda:0")
     xt = torch.from_numpy(x).to(dev)
     torch.cuda.synchronize()
+    if args.copy_probe:
+        src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = pc.Context(0)
     stream = torch.cuda.current_stream(dev).cuda_stream
 
@@ -206,20 +283,7 @@ def main():
     roof = None
     if cands:
         ms, link, kname, nl, sts = cands[0]
-        avg_ms = ms / nl
-        if kname == "pair_tiles":
-            work = sum(s["point_pair_evals"] for s in sts) * COMPLETE_PAIR_FLOPS / nl
-            achieved = work / (avg_ms / 1000.0) / 1e12
-            roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VEC_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VEC_TFLOPS, "traffic": None}
-        else:
-            work = sum(s["kernels"][kname]["visits"] for s in sts) * visit_bytes(link) / nl
-            achieved = work / (avg_ms / 1000.0) / 1e9
-            roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-        roof.update({"kernel": kname, "linkage": link, "avg_launch_ms": avg_ms, "launches": nl,
-                     "work_per_launch": work,
-                     "note": "search kernels gather candidate records; work = visits x record bytes"})
+        roof = roofline(kname, link, d, ms, nl, sts)
 
     value = n * len(links) / (wall / max(args.steps, 1))
     out = {
@@ -235,9 +299,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64 (float32 inputs)",
         "data": "synthetic",
-        "config": {"workload": "blob50_1m_d2: n=1,000,000 d=2, 50 Gaussians sigma=0.01, seed 11; "
-                               "Ward + complete linkage per step", "n": n, "d": 2,
-                   "linkages": links, "parallelism": "single GPU"},
+        "config": {"workload": ("blob50_1m_d2: n=1,000,000 d=2, 50 Gaussians sigma=0.01, seed 11; "
+                                "Ward + complete linkage per step") if args.workload == "blob50_1m_d2"
+                   else "%s (%s linkage per step)" % (args.workload, "+".join(links)),
+                   "n": int(n), "d": int(d), "linkages": links, "parallelism": "single GPU"},
         "linkage_dist_evals_per_s": tot_evals / wall,
         "per_linkage": lk,
         "roofline": roof,

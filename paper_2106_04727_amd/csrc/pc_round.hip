@@ -3132,11 +3132,11 @@ template <int LINK>
 void launch_gram_refine_t(State &S, int ncand, hipStream_t s) {
   if constexpr (LINK != kWard) {
     if (!S.p16 || ncand <= 0) goto exact;
-    tmark(S, 1, false, s);
     k_cand_triage<LINK><<<nblk(ncand, 4096), kBlock, 0, s>>>(S, ncand);
     k_cand_small<LINK><<<8192, kBlock, 0, s>>>(S);
     k_scr_count<<<1, 1, 0, s>>>(S.cnt);
     scan_exclusive_i64(S.cd_tile0, S.cd_tile0, ncand, &S.cnt->n_scr32, &S.cnt->n_ctiles, S.part, s);
+    tmark(S, 1, false, s);  // the interval tiles alone
     switch (S.gkp) {
     case 16: launch_cand_tiles<LINK, 16>(S, ncand, s); break;
     case 32: launch_cand_tiles<LINK, 32>(S, ncand, s); break;
@@ -3145,8 +3145,8 @@ void launch_gram_refine_t(State &S, int ncand, hipStream_t s) {
     case 128: launch_cand_tiles<LINK, 128>(S, ncand, s); break;
     default: launch_cand_tiles<LINK, 144>(S, ncand, s); break;
     }
-    k_cand_bound<LINK><<<nblk(ncand, 4096), kBlock, 0, s>>>(S);
     tmark(S, 1, true, s);
+    k_cand_bound<LINK><<<nblk(ncand, 4096), kBlock, 0, s>>>(S);
   }
 exact:
   tmark(S, 3, false, s);
