@@ -13,7 +13,11 @@ Also reported (one JSON line):
                 launch time, against MI355X's published peak
   cpu_baseline  the FP64 oracle (sequential NN-chain, OpenMP candidate scan)
                 timed on this host's cores on a bounded sample of the same law
-Extra, outside the timed steps: the 10,000,000-point Ward run of the same law.
+Extra, outside the timed steps: the 10,000,000-point Ward run of the same law;
+one run each of the d = 10 (1M uniform, average) and d = 128 (200K unit
+vectors, Ward / complete / average) workloads with their dominant kernel's
+roofline; the serving leg (a trace of requests of uneven n, d and linkage:
+one at a time, open loop with p50/p99 latency, all at once).
 """
 from __future__ import annotations
 
@@ -110,6 +114,30 @@ def measured_traffic(kname, link, d):
     return float(vals["hbm_bytes_per_launch"])
 
 
+def workload_leg(pc, synth, torch, ctx, stream, wl, link):
+    """One timed run of another configuration (after a small warm-up of the
+    same dimension), inputs resident on the device; with its dominant kernel's
+    roofline entry."""
+    x = synth.WORKLOADS[wl]()
+    n, d = x.shape
+    dev = torch.device("cuda:0")
+    w = torch.from_numpy(synth.blobs(4000, d, 20, 0.03, 3)).to(dev)
+    pc.hac_device(w, link, ctx=ctx, stream=stream)
+    xt = torch.from_numpy(x).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = pc.hac_device(xt, link, ctx=ctx, stream=stream, timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    best = max(KERNEL_NAMES, key=lambda k: st["kernels"][k]["ms"])
+    roof = roofline(best, link, d, st["kernels"][best]["ms"], max(st["kernels"][best]["launches"], 1), [st])
+    del xt
+    return {"n": int(n), "d": int(d), "linkage": link, "s": wall, "points_per_s": n / wall,
+            "rounds": st["rounds"], "cluster_evals": st["cluster_evals"],
+            "point_pair_evals": st["point_pair_evals"], "cache_hits": st["cache_hits"],
+            "cache_derived": st["cache_derived"], "kernels": st["kernels"], "roofline": roof}
+
+
 def serve_bench(num, slots, n_max):
     """Serving leg: a Poisson trace of clustering requests of uneven n, d and
     linkage (the serving law of ``synth.serving_trace``), first solved one at
@@ -192,7 +220,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 10M Ward run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 10M Ward run and the d=10 / d=128 workloads")
     ap.add_argument("--links", default=",".join(LINKS))
     ap.add_argument("--serve-requests", type=int, default=40,
                     help="requests of the serving trace (0 skips the serving leg)")
@@ -320,6 +349,15 @@ def main():
             del x10t
         except Exception as e:  # reported, never hidden
             out["ward_10m"] = {"error": str(e)}
+
+    if not args.no_extra and args.workload == "blob50_1m_d2":
+        out["workloads"] = {}
+        for wl, link in (("u1m_d10", "average"), ("vmf1000_200k_d128", "ward"),
+                         ("vmf1000_200k_d128", "complete"), ("vmf1000_200k_d128", "average")):
+            try:
+                out["workloads"]["%s_%s" % (wl, link)] = workload_leg(pc, synth, torch, ctx, stream, wl, link)
+            except Exception as e:  # reported, never hidden
+                out["workloads"]["%s_%s" % (wl, link)] = {"error": str(e)}
 
     if args.serve_requests > 0:
         try:

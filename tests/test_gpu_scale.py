@@ -127,3 +127,83 @@ def test_ward_10m_blobs(pc):
     x = synth.blobs(10_000_000, 2, 50, 0.01, 12)
     Z = pc.hac(x, "ward")
     ward_check(x, Z, sample_rows(Z.shape[0], 12, 3))
+
+
+def alive_labels(Z, n, r):
+    """For every point, the node that holds it just before row r."""
+    parent = np.arange(2 * n - 1, dtype=np.int64)
+    a = Z[:r, 0].astype(np.int64)
+    b = Z[:r, 1].astype(np.int64)
+    parent[a] = n + np.arange(r)
+    parent[b] = n + np.arange(r)
+    lab = parent[:n].copy()
+    while True:
+        nxt = parent[lab]
+        if np.array_equal(nxt, lab):
+            return lab
+        lab = nxt
+
+
+def linkage_to_all(x, X, lab, link):
+    """Linkage distance from point set X to every node alive under `lab`, in
+    FP64 from all point distances (numpy)."""
+    P = x[X].astype(np.float64)
+    Q = x.astype(np.float64)
+    d2 = (P * P).sum(1)[:, None] + (Q * Q).sum(1)[None, :] - 2.0 * P @ Q.T
+    D = np.sqrt(np.maximum(d2, 0.0))
+    nodes, inv = np.unique(lab, return_inverse=True)
+    if link == "average":
+        s = np.bincount(inv, weights=D.sum(0), minlength=nodes.size)
+        cnt = np.bincount(inv, minlength=nodes.size)
+        return nodes, s / (cnt * len(X))
+    m = np.zeros(nodes.size)
+    np.maximum.at(m, inv, D.max(0))
+    return nodes, m
+
+
+def nn_check(x, Z, link, rows, max_side=400):
+    n = x.shape[0]
+    checked = 0
+    for r in rows:
+        A, B, h = int(Z[r, 0]), int(Z[r, 1]), Z[r, 2]
+        MA, MB = oracle.node_members(Z, n, A), oracle.node_members(Z, n, B)
+        X = MA if MA.size <= MB.size else MB
+        if X.size > max_side:
+            continue
+        if MA.size * MB.size <= 2e7:
+            ho = oracle.linkage_dist(x, link, MA, MB)
+            assert ho == pytest.approx(h, rel=1e-12 if link == "average" else 0.0, abs=0.0), r
+        lab = alive_labels(Z, n, r)
+        nodes, vals = linkage_to_all(x, X, lab, link)
+        keep = (nodes != A) & (nodes != B)
+        # the merged pair is a nearest pair among the clusters alive at that time
+        assert vals[keep].min() >= h * (1 - 1e-9), (r, vals[keep].min(), h)
+        checked += 1
+    assert checked >= 3
+
+
+def full_size_rows(Z, seed, k=10):
+    rng = np.random.default_rng(seed)
+    m = Z.shape[0]
+    return sorted(set(rng.choice(m, size=k, replace=False).tolist()) | {m // 2, m - m // 10})
+
+
+@pytest.mark.parametrize("link", ["complete", "average"])
+def test_c4_d128_200k(pc, link):
+    """200,000 unit vectors in d = 128 around 1,000 centres (the C4 workload)."""
+    x = synth.WORKLOADS["vmf1000_200k_d128"]()
+    Z = pc.hac(x, link)
+    n = x.shape[0]
+    _, sizes = oracle.tree_sums(x, Z)
+    structure(Z, n, sizes)
+    nn_check(x, Z, link, full_size_rows(Z, 7))
+
+
+def test_c3_d10_1m_average(pc):
+    """1,000,000 uniform points in [0,1]^10, average linkage (the C3 workload)."""
+    x = synth.WORKLOADS["u1m_d10"]()
+    Z = pc.hac(x, "average")
+    n = x.shape[0]
+    _, sizes = oracle.tree_sums(x, Z)
+    structure(Z, n, sizes)
+    nn_check(x, Z, "average", full_size_rows(Z, 8, k=6), max_side=100)
