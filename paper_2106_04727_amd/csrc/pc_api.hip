@@ -469,6 +469,10 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   HIPCHK(hipEventRecord(ctx->ev[1], s));
 
   const bool debug = getenv("PC_DEBUG") != nullptr;
+  // tuning knob: cells a thread-per-terminal ring search visits before it
+  // hands the terminal to the block search
+  S.cell_budget = linkage == kWard ? 24 : 160;  // measured on the 1M 2-D workload
+  if (const char *e = getenv("PC_CELL_BUDGET")) S.cell_budget = std::max(1, atoi(e));
   long long gram_batch = 0;  // terminals per Gram batch (0: all), kept across rounds
   // test hook: small batches exercise the batch loop on small inputs
   if (const char *e = getenv("PC_TEST_GRAM_BATCH")) gram_batch = std::max<long long>(1, atoll(e));

@@ -214,7 +214,8 @@ struct State {
   unsigned long long *gmin, *gmax;  // per-dimension ordered bits of the centroid range
   double *gscale;       // 1 value
   int *term_pos;        // active-list index of each terminal
-  int tb0, tb1;         // terminals [tb0, tb1) of the current Gram batch
+  int tb0, tb1;      // terminals [tb0, tb1) of the current Gram batch
+  int cell_budget;  // grid cells a thread-per-terminal search visits before handing off
   double *tile_v;
   long long pair_cap, tile_cap;
   int cell_cap;

@@ -31,7 +31,7 @@ namespace pc {
 
 namespace {
 
-constexpr int kCellBudget = 160;        // cells a thread may visit before handing off
+constexpr int kCellBudget = 160;        // default: cells a thread may visit before handing off
 constexpr double kSlack = 1.0 + 1e-9;   // bounds are applied with this margin
 constexpr unsigned long long kNoKey = ~0ull;
 
@@ -814,7 +814,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
           if (lbk > cur) break;
         }
         visited += k == 0 ? 1 : 8 * k;
-        if (PASS == 0 && visited > kCellBudget) {
+        if (PASS == 0 && visited > S.cell_budget) {
           overflow = true;
           break;
         }
@@ -906,10 +906,23 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                 }
                 if (cost <= kInlinePairs) {
                   if (PASS == 0) {
-                    const int beg_c = S.cbeg[s];
-                    const double v = (mt.z < cid_t)
-                                         ? pair_exact_inline<LINK>(S.px, d, beg_c, mt.y, beg_t, n_t)
+                    double v;
+                    if (cost == 1) {
+                      // two singletons: the FP64 centroids are the widened points, so
+                      // this is the same sum as the point-pair evaluation
+                      double q = 0.0;
+#pragma unroll
+                      for (int k = 0; k < MAXD; ++k)
+                        if (k < d) {
+                          const double u = ct[k] - cv[k];
+                          q += u * u;
+                        }
+                      v = LINK == kComplete ? q : sqrt(q);
+                    } else {
+                      const int beg_c = S.cbeg[s];
+                      v = (mt.z < cid_t) ? pair_exact_inline<LINK>(S.px, d, beg_c, mt.y, beg_t, n_t)
                                          : pair_exact_inline<LINK>(S.px, d, beg_t, n_t, beg_c, mt.y);
+                    }
                     ++evals;
                     ppairs += cost;
                     if (better(v, key, bestv, bestk)) {
