@@ -343,6 +343,20 @@ __global__ void k_cell_count(State S) {
   }
 }
 
+// Mean squared deviation of a cluster's points from its centroid (Var/|C|,
+// the merge rule of Sec. 2.1), lowered by a relative 1e-6 for FP64 rounding:
+// complete linkage's key is at least ||cA - cB||^2 + this for both clusters
+// (the mean squared point distance never exceeds the largest).
+__device__ __forceinline__ double spread_lo(const State &S, int s) {
+  return S.cvar[s] / (double)S.csize[s] * (1.0 - 1e-6);
+}
+
+__device__ __forceinline__ int spread_bits(double v) {
+  float f = (float)v;
+  if ((double)f > v) f = nextafterf(f, 0.0f);
+  return __float_as_int(f);
+}
+
 __global__ void k_cell_scatter(State S) {
   const int nact = S.cnt->n_act;
   const int d = S.d;
@@ -354,7 +368,7 @@ __global__ void k_cell_scatter(State S) {
       continue;
     }
     S.item_slot[pos] = s;
-    S.item_meta[pos] = make_int4(s, S.csize[s], S.cid[s], 0);
+    S.item_meta[pos] = make_int4(s, S.csize[s], S.cid[s], S.linkage == kComplete ? spread_bits(spread_lo(S, s)) : 0);
     for (int k = 0; k < d; ++k) S.item_cen[(size_t)pos * d + k] = S.wcen[(size_t)s * d + k];
     if (S.linkage != kWard)
       for (int k = 0; k < d; ++k) {
@@ -411,13 +425,15 @@ __device__ double pair_exact_inline(const float *px, int d, int begR, int nR, in
 
 // Lower and upper bounds of a pair's key from centroids and tight boxes.
 //   complete (squared units): LB = max(centroid distance, per-axis extent
-//     max(hiC-loT, hiT-loC)) -- every per-axis extent is attained by a real
-//     point pair; UB = squared max distance between the boxes.
+//     max(hiC-loT, hiT-loC) -- every per-axis extent is attained by a real
+//     point pair --, centroid distance + both spreads vs); UB = squared max
+//     distance between the boxes.
 //   average: LB = max(centroid distance (Sec. 4.2), min box distance);
 //     UB = max box distance.
 template <int LINK, int MAXD>
 __device__ __forceinline__ void pair_bounds(const double *ct, const float *lt, const float *ht, const double *cc,
-                                            const float *lc, const float *hc, int d, double &lb, double &ub) {
+                                            const float *lc, const float *hc, int d, double &lb, double &ub,
+                                            double vs = 0.0) {
   double cdist = 0.0, ext = 0.0, mind = 0.0, maxd = 0.0;
   const int D = MAXD > 0 ? MAXD : d;
 #pragma unroll
@@ -436,6 +452,8 @@ __device__ __forceinline__ void pair_bounds(const double *ct, const float *lt, c
   if (LINK == kComplete) {
     double e2 = ext * ext;
     lb = cdist > e2 ? cdist : e2;
+    const double sp = cdist * (1.0 - 1e-6) + vs;  // vs: both spreads, lowered
+    lb = sp > lb ? sp : lb;
     ub = maxd;
   } else {
     double c1 = sqrt(cdist), m1 = sqrt(mind);
@@ -779,6 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
       }
     }
     const int beg_t = LINK != kWard ? S.cbeg[t] : 0;
+    const double sp_t = LINK == kComplete ? spread_lo(S, t) : 0.0;
     bool skip = false;
     double bound;
     double bestv = INFINITY;
@@ -809,7 +828,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
       for (int k = 0; k <= kmax && !overflow; ++k) {
         if (k >= 1) {
           const double D = fmax(0.0, ((double)(k - 1) + m) * g.h * (1.0 - 1e-9) - g.eps);
-          const double lbk = ring_key_lb<LINK>(D, nt, nmin);
+          const double lbk = ring_key_lb<LINK>(D, nt, nmin) + sp_t;  // complete: + own spread
           const double cur = PASS == 0 ? fmin(bound, bestv) : bound;
           if (lbk > cur) break;
         }
@@ -870,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                   hc[q] = q < d ? S.item_hi[(size_t)it * d + q] : 0.f;
                 }
                 double lb, ub;
-                pair_bounds<LINK, MAXD>(ct, lt, ht, cv, lc, hc, d, lb, ub);
+                pair_bounds<LINK, MAXD>(ct, lt, ht, cv, lc, hc, d, lb, ub, sp_t + (double)__int_as_float(mt.w));
                 const double cur = PASS == 0 ? fmin(bound, bestv) : bound;
                 if (lb > cur * kSlack) continue;
                 const long long cost = (long long)n_t * (long long)mt.y;
@@ -1073,6 +1092,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
       ht[k] = (LINK != kWard && k < d) ? S.hi[(size_t)t * d + k] : 0.f;
     }
     const int beg_t = LINK != kWard ? S.cbeg[t] : 0;
+    const double sp_t = LINK == kComplete ? spread_lo(S, t) : 0.0;
     const int cx = cell_coord(ct[0], g.org[0], g.inv_h, g.G[0]);
     const int cy = g.axes == 2 ? cell_coord(ct[1], g.org[1], g.inv_h, g.G[1]) : 0;
     const int kmax = max(max(cx, g.G[0] - 1 - cx), max(cy, g.G[1] - 1 - cy));
@@ -1122,7 +1142,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
           }
           const double Dc = fmax(0.0, sqrt(dx * dx + dy * dy) * (1.0 - 1e-9) - g.eps);
           const double mycur = pass == 0 ? fmin(cur, fmin(bound, bestv)) : cur;
-          if (cell_key_lb<LINK>(Dc, nt, S.cell_nmin[cell]) > mycur) continue;
+          if (cell_key_lb<LINK>(Dc, nt, S.cell_nmin[cell]) + sp_t > mycur) continue;
           visits += b - a;
           for (int it = a; it < b; ++it) {
             const int4 mt = S.item_meta[it];
@@ -1148,7 +1168,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
                 hc[q] = q < d ? S.item_hi[(size_t)it * d + q] : 0.f;
               }
               double lb, ub;
-              pair_bounds<LINK, MAXD>(ct, lt, ht, cv, lc, hc, d, lb, ub);
+              pair_bounds<LINK, MAXD>(ct, lt, ht, cv, lc, hc, d, lb, ub, sp_t + (double)__int_as_float(mt.w));
               const double c2 = pass == 0 ? fmin(cur, fmin(bound, bestv)) : cur;
               if (lb > c2 * kSlack) continue;
               const long long cost = (long long)n_t * (long long)mt.y;
@@ -1257,7 +1277,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
             }
           }
           const double D = fmax(0.0, ((double)k + m) * g.h * (1.0 - 1e-9) - g.eps);
-          if (ring_key_lb<LINK>(D, nt, (double)S.cnt->n_min) > cur) break;
+          if (ring_key_lb<LINK>(D, nt, (double)S.cnt->n_min) + sp_t > cur) break;
         }
       }
       if (LINK == kWard && pass == 0 && bestk == kNoKey && use_pred) {
@@ -1339,7 +1359,8 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
         }
       } else {
         double lb, ub;
-        pair_bounds<LINK, 0>(ct, lt, ht, cc, S.lo + (size_t)s * d, S.hi + (size_t)s * d, d, lb, ub);
+        pair_bounds<LINK, 0>(ct, lt, ht, cc, S.lo + (size_t)s * d, S.hi + (size_t)s * d, d, lb, ub,
+                             LINK == kComplete ? spread_lo(S, t) + spread_lo(S, s) : 0.0);
         if (S.prune && lb > fmin(bound, bestv) * kSlack) continue;
         const long long cost = (long long)n_t * n_c;
         if (cost > kInlinePairs && S.cache_mask) {
@@ -1422,7 +1443,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
         if (S.prune) {
           double lb, ub;
           pair_bounds<LINK, 0>(ct, lt, ht, S.wcen + (size_t)s * d, S.lo + (size_t)s * d, S.hi + (size_t)s * d,
-                               d, lb, ub);
+                               d, lb, ub, LINK == kComplete ? spread_lo(S, t) + spread_lo(S, s) : 0.0);
           if (lb > beta * kSlack) continue;
           if (LINK == kComplete) {
             comp_lb_refine(S, t, s, d, lb, beta * kSlack);
@@ -1593,7 +1614,7 @@ __global__ void k_pair_prep_comp(State S, long long *nch) {
       const double *cr = S.wcen + (size_t)r * d, *cq = S.wcen + (size_t)q * d;
       double lb, ub;
       pair_bounds<kComplete, 0>(cr, S.lo + (size_t)r * d, S.hi + (size_t)r * d, cq, S.lo + (size_t)q * d,
-                                S.hi + (size_t)q * d, d, lb, ub);
+                                S.hi + (size_t)q * d, d, lb, ub, spread_lo(S, r) + spread_lo(S, q));
       comp_lb_refine(S, r, q, d, lb);
       S.pr_v[p] = lb;
     }
