@@ -1568,7 +1568,7 @@ __global__ __launch_bounds__(kBlock) void k_tiles_avg(State S, long long ntiles)
           for (int k = 0; k < MD; ++k)
             if (k < d) {
               double u = rows[w][rr][k] - cv[k];
-              qd += u * u;
+              qd = __builtin_fma(u, u, qd);  // average: held to 1e-12, not bitwise
             }
           acc += sqrt(qd);
         }
@@ -1856,7 +1856,10 @@ __global__ __launch_bounds__(kBlock) void k_tiles_hd(State S) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const double u = ar[a] - br[b];
-          q[a][b] += u * u;
+          // complete: separate multiply and add (bit-identical maxima);
+          // average: fused (held to 1e-12)
+          if (LINK == kAverage) q[a][b] = __builtin_fma(u, u, q[a][b]);
+          else q[a][b] += u * u;
         }
     }
     double part = LINK == kAverage ? 0.0 : -1.0;
@@ -3364,7 +3367,6 @@ void launch_pairs(State &S, int round, int npairs, long long work, hipStream_t s
       tmark(S, 2, false, s);
       if (S.d <= 2) k_tiles_avg<2><<<tb, kBlock, 0, s>>>(S, ntiles);
       else if (S.d <= 4) k_tiles_avg<4><<<tb, kBlock, 0, s>>>(S, ntiles);
-      else if (S.d <= 16) k_tiles_avg<16><<<tb, kBlock, 0, s>>>(S, ntiles);
       else if (S.d <= kGramMaxDim) k_tiles_hd<kAverage><<<(int)std::min<long long>(ntiles, 8192), kBlock, 0, s>>>(S);
       else k_tiles_avg<0><<<tb, kBlock, 0, s>>>(S, ntiles);
       tmark(S, 2, true, s);
