@@ -66,6 +66,7 @@ def test_fig1_worked_example(pc):
     (2, 2, "u", 1), (3, 2, "u", 2), (64, 2, "u", 3), (257, 1, "u", 4), (1000, 2, "b", 5),
     (2000, 3, "u", 6), (3000, 10, "b", 7), (700, 16, "u", 8), (500, 40, "b", 9),
     (1500, 4, "u", 10), (2000, 64, "b", 11), (2500, 128, "s", 12), (800, 100, "s", 13),
+    (400, 200, "b", 14),  # beyond the Gram search: full scan and generic tiles
 ])
 def test_parity_small(pc, link, n, d, kind, seed):
     if kind == "u":
