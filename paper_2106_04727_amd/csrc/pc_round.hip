@@ -1892,11 +1892,20 @@ __global__ __launch_bounds__(kBlock) void k_pair_finish(State S, int link) {
   const int wave0 = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int nwaves = (gridDim.x * blockDim.x) / kWave;
   long long evals = 0;
+  if (link == kComplete) {
+    // the value is already in place (tile maxima): a thread per pair
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+      const double v = S.pr_v[p];
+      atomicMin(&S.t_min[S.pr_t[p]], pos_bits(v));
+      ++evals;
+      if (S.cache_mask) cache_fill(S, pair_key(S.node[S.term[S.pr_t[p]]], S.node[S.pr_c[p]]), v);
+    }
+    count_add(&S.cnt->cluster_evals, evals);
+    return;
+  }
   for (int p = wave0; p < np; p += nwaves) {
     double v;
-    if (link == kComplete) {
-      v = S.pr_v[p];
-    } else {
+    {
       const long long a = S.pr_tile0[p], b = (p + 1 < np) ? S.pr_tile0[p + 1] : S.cnt->n_tiles;
       double s = 0.0;
       for (long long g = a + lane; g < b; g += kWave) s += S.tile_v[g];
@@ -3371,7 +3380,8 @@ void launch_pairs(State &S, int round, int npairs, long long work, hipStream_t s
       else k_tiles_avg<0><<<tb, kBlock, 0, s>>>(S, ntiles);
       tmark(S, 2, true, s);
     }
-    k_pair_finish<<<nblk((long long)npairs * kWave, 4096), kBlock, 0, s>>>(S, S.linkage);
+    k_pair_finish<<<S.linkage == kComplete ? nblk(npairs, 2048) : nblk((long long)npairs * kWave, 4096), kBlock, 0,
+                    s>>>(S, S.linkage);
   }
   if (S.cache_mask) k_pending_min<<<2048, kBlock, 0, s>>>(S);
   k_term_key_reset<<<nblk(S.n, 2048), kBlock, 0, s>>>(S);
