@@ -183,12 +183,51 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const unsigned long lo
 
 inline int blocks_for(long long n, int tile) { return (int)((n + tile - 1) / tile); }
 
+// Short scans (at most kSingleScan elements): one block walks the tiles in
+// order, so a scan costs one launch instead of three (late rounds are short).
+constexpr int kSingleScan = 4 * kScanTile;
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_scan_single(const T *in, T *out, int nmax, const int *dlen,
+                                                        long long *total64, int *total32) {
+  const int len = scan_len<T>(nmax, dlen);
+  T carry = 0;
+  for (int b0 = 0; b0 < len; b0 += kScanTile) {
+    T v[kScanItems];
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const int i = b0 + threadIdx.x * kScanItems + j;
+      v[j] = i < len ? in[i] : (T)0;
+      s += v[j];
+    }
+    T tot;
+    const T ex = block_exclusive_scan<T>(s, tot);
+    T run = carry + ex;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const int i = b0 + threadIdx.x * kScanItems + j;
+      if (i < len) out[i] = run;
+      run += v[j];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    if (total64) *total64 = (long long)carry;
+    if (total32) *total32 = (int)carry;
+  }
+}
+
 }  // namespace
 
 void scan_exclusive_i32(const int *in, int *out, int nmax, const int *dlen, int *dtotal,
                         long long *part, hipStream_t s) {
   if (nmax <= 0) {
     if (dtotal) hipMemsetAsync(dtotal, 0, sizeof(int), s);
+    return;
+  }
+  if (nmax <= kSingleScan) {
+    k_scan_single<int><<<1, kBlock, 0, s>>>(in, out, nmax, dlen, nullptr, dtotal);
     return;
   }
   const int nb = blocks_for(nmax, kScanTile);
@@ -201,6 +240,10 @@ void scan_exclusive_i64(const long long *in, long long *out, int nmax, const int
                         long long *dtotal, long long *part, hipStream_t s) {
   if (nmax <= 0) {
     if (dtotal) hipMemsetAsync(dtotal, 0, sizeof(long long), s);
+    return;
+  }
+  if (nmax <= kSingleScan) {
+    k_scan_single<long long><<<1, kBlock, 0, s>>>(in, out, nmax, dlen, dtotal, nullptr);
     return;
   }
   const int nb = blocks_for(nmax, kScanTile);

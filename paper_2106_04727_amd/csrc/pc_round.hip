@@ -273,6 +273,13 @@ __global__ void k_scatter_flagged(const int *src, const int *flags, const int *p
 }
 
 // ------------------------------------------------------------------ grid --
+// at most this many cells: the cell scan's length is then known on the host
+// from the previous round's active count (an upper bound of this round's)
+__host__ __device__ __forceinline__ int grid_cells_max(int cell_cap, int nact) {
+  const long long m = 4LL * nact + 16;
+  return m < cell_cap ? (int)m : cell_cap;
+}
+
 __global__ void k_grid_params(State S, int cell_cap) {
   GridParams g;
   const int axes = S.d >= 2 ? 2 : 1;
@@ -293,7 +300,7 @@ __global__ void k_grid_params(State S, int cell_cap) {
   int G0, G1;
   for (;;) {
     double g0 = floor(ext[0] / h) + 1.0, g1 = axes == 2 ? floor(ext[1] / h) + 1.0 : 1.0;
-    if (g0 * g1 <= (double)cell_cap) {
+    if (g0 * g1 <= (double)grid_cells_max(cell_cap, nact)) {
       G0 = (int)g0;
       G1 = (int)g1;
       break;
@@ -3302,7 +3309,8 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
     k_zero_cells<<<nblk(nact + 1, 2048), kBlock, 0, s>>>(S);
     k_cell_count<<<gb, kBlock, 0, s>>>(S);
     // cells <= cell_cap; scan length ncell + 1 (the extra zero gives the total)
-    scan_exclusive_i32(S.cell_cnt, S.cell_start, S.cell_cap + 1, &S.grid->ncell1, nullptr, S.part, s);
+    scan_exclusive_i32(S.cell_cnt, S.cell_start, grid_cells_max(S.cell_cap, nact) + 1, &S.grid->ncell1, nullptr,
+                       S.part, s);
     k_cell_scatter<<<gb, kBlock, 0, s>>>(S);
   }
   int *t_ovf = S.cell_rank;  // per-terminal hand-off flags (cell ranks are no longer needed)
