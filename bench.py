@@ -16,7 +16,8 @@ Also reported (one JSON line):
 Extra, outside the timed steps: the 10,000,000-point Ward run of the same law;
 one run each of the d = 10 (1M uniform, average) and d = 128 (200K unit
 vectors, Ward / complete / average) workloads with their dominant kernel's
-roofline; the serving leg (a trace of requests of uneven n, d and linkage:
+roofline; one run each on the paper's own synthetic laws (2U1M, 2G1M, 5U1M,
+5G1M, 2U10M, 2G10M) beside its 48-core times; the serving leg (a trace of requests of uneven n, d and linkage:
 one at a time, open loop with p50/p99 latency, all at once).
 """
 from __future__ import annotations
@@ -136,6 +137,33 @@ def workload_leg(pc, synth, torch, ctx, stream, wl, link):
             "rounds": st["rounds"], "cluster_evals": st["cluster_evals"],
             "point_pair_evals": st["point_pair_evals"], "cache_hits": st["cache_hits"],
             "cache_derived": st["cache_derived"], "kernels": st["kernels"], "roofline": roof}
+
+
+# The paper's 48-core (two-way hyper-threaded) running times in seconds on its
+# own synthetic sets (Sec. 6, table of running times), for context only:
+# another machine, and inputs drawn here from the same laws, not the same files.
+PAPER_48H_S = {
+    ("2U1M", "ward"): 0.50, ("2G1M", "ward"): 0.52, ("5U1M", "ward"): 1.95, ("5G1M", "ward"): 2.69,
+    ("2U10M", "ward"): 5.69, ("2G10M", "ward"): 5.20,
+    ("2U1M", "complete"): 1.34, ("2G1M", "complete"): 1.61, ("2U10M", "complete"): 19.01,
+    ("2G10M", "complete"): 21.29,
+    ("2U1M", "average"): 23.59, ("2G1M", "average"): 26.83, ("5U1M", "average"): 38.10,
+    ("5G1M", "average"): 45.27,
+}
+
+
+def paper_leg(pc, synth, torch, ctx, stream):
+    """One run each on the paper's synthetic laws (UniformFill, GaussianDisc)
+    beside the paper's 48-core time for the same set name."""
+    out = {}
+    for (wl, link), ref in PAPER_48H_S.items():
+        try:
+            r = workload_leg(pc, synth, torch, ctx, stream, wl, link)
+            out["%s_%s" % (wl, link)] = {"s": r["s"], "rounds": r["rounds"], "paper_48h_s": ref,
+                                         "ratio_paper_over_ours": ref / r["s"]}
+        except Exception as e:  # reported, never hidden
+            out["%s_%s" % (wl, link)] = {"error": str(e)}
+    return out
 
 
 def serve_bench(num, slots, n_max):
@@ -358,6 +386,9 @@ def main():
                 out["workloads"]["%s_%s" % (wl, link)] = workload_leg(pc, synth, torch, ctx, stream, wl, link)
             except Exception as e:  # reported, never hidden
                 out["workloads"]["%s_%s" % (wl, link)] = {"error": str(e)}
+
+    if not args.no_extra and args.workload == "blob50_1m_d2":
+        out["paper_sets"] = paper_leg(pc, synth, torch, ctx, stream)
 
     if args.serve_requests > 0:
         try:

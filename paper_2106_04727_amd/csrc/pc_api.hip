@@ -388,7 +388,11 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   S.linkage = linkage;
   S.prune = prune;
   S.timing = (opt && opt->timing) ? 1 : 0;
-  S.gram = (prune && d >= kGramMinDim && d <= kGramMaxDim) ? 1 : 0;
+  // Ward keeps the centroid grid through d = 5 (measured faster there than
+  // the Gram search on 1M-point 5-D sets); tuning knob PC_GRAM_MIN_DIM
+  int gram_min = linkage == kWard ? 6 : kGramMinDim;
+  if (const char *e = getenv("PC_GRAM_MIN_DIM")) gram_min = std::max(kGramMinDim, atoi(e));
+  S.gram = (prune && d >= gram_min && d <= kGramMaxDim) ? 1 : 0;
   S.tev = ctx->tev;
   S.xin = nullptr;  // set once the device copy of the points is known
   double kms[4] = {0, 0, 0, 0};
@@ -503,13 +507,16 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
       if (linkage == kComplete) {
         work = np > 0 ? h.n_chunks : 0;
         if (work * kChunk > S.fidx_cap) {
-          pc_status st = grow_fidx(ctx, S, work * kChunk + work * kChunk / 2 + 1024);
+          // headroom for later rounds, within the limit
+          const long long want = std::min<long long>(work * kChunk + work * kChunk / 2 + 1024, 8 * kMaxRecord);
+          pc_status st = grow_fidx(ctx, S, std::max<long long>(want, work * kChunk));
           if (st != PC_OK) return st;
         }
       } else {
         work = np > 0 ? h.n_tiles : 0;
         if (work > S.tile_cap) {
-          pc_status st = grow_tiles(ctx, S, work + work / 2 + 1024);
+          const long long want = std::min<long long>(work + work / 2 + 1024, 4 * kMaxRecord);
+          pc_status st = grow_tiles(ctx, S, std::max<long long>(want, work));
           if (st != PC_OK) return st;
         }
       }
@@ -617,7 +624,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
         S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;  // the round is redone
         launch_cache_unclaim(S, s);
         const long long want = std::max<long long>(h.n_pairs, h.n_pend);
-        pc_status st = grow_pairs(ctx, S, want + want / 2 + 1024);
+        pc_status st = grow_pairs(ctx, S, std::max<long long>(want, std::min<long long>(want + want / 2 + 1024, kMaxRecord)));
         if (st != PC_OK) return st;
         launch_round(S, (int)rounds, nact, s, need_pairs);
         HIPCHK(hipGetLastError());

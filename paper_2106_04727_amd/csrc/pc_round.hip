@@ -2416,7 +2416,9 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
 // tile; complete takes the largest d2. Each terminal's bound drops to its
 // smallest H, and only candidates with L <= bound are evaluated exactly.
 constexpr long long kIntervalWork = 16384;  // point pairs x d from which a pair is screened first
-constexpr int kIntervalMinDim = 32;         // below it exact FP64 tiles are cheaper than screening
+constexpr int kIntervalMinDim = 32;         // average: below it exact FP64 tiles are cheaper than screening
+                                            // (complete screens at every Gram dimension: its tile
+                                            // maximum brackets tightly and costs ~3 ops per pair)
 
 // per-dimension range of all points (once per call)
 __global__ void k_pt_range(const float *x, int n, int d, unsigned long long *gmin, unsigned long long *gmax) {
@@ -2506,7 +2508,7 @@ __global__ void k_cand_triage(State S, int ncand) {
     if (cost <= kInlinePairs) {
       const long long k = append_slot(&S.cnt->n_small);
       S.cd_small[k] = i;  // k < ncand: every candidate appends at most once
-    } else if (d >= kIntervalMinDim && cost * d >= kIntervalWork) {
+    } else if (d >= (LINK == kComplete ? kGramMinDim : kIntervalMinDim) && cost * d >= kIntervalWork) {
       // dense list of screened candidates: tile count, point ranges, index
       const long long k = append_slot(&S.cnt->n_scr);
       S.cd_tile0[k] = (long long)((nt + kGT - 1) / kGT) * ((nc + kGT - 1) / kGT);

@@ -17,6 +17,13 @@ GaussianDisc sets and for its real data sets, none of which are reproduced):
                 [0,1]^d, equal weights, standard deviation ``sigma``.
 * ``sphere_blobs``  unit-norm vectors around ``k`` random unit centres
                 (Gaussian noise of std ``sigma``, then renormalised).
+* ``uniform_fill``  the paper's UniformFill law (Sec. 6 data sets): uniform
+                in a hypergrid of side sqrt(n).
+* ``gaussian_disc`` the paper's GaussianDisc law: a hypergrid of side
+                5 sqrt(n); 90% of the points split equally among five
+                Gaussians with means uniform in the hypergrid and standard
+                deviation sqrt(n)/6 (so that the stated diameter sqrt(n) is six
+                standard deviations), the other 10% uniform in the hypergrid.
 """
 from __future__ import annotations
 
@@ -26,6 +33,8 @@ __all__ = [
     "uniform",
     "blobs",
     "sphere_blobs",
+    "uniform_fill",
+    "gaussian_disc",
     "dedup_rows",
     "workload",
     "WORKLOADS",
@@ -87,6 +96,32 @@ def sphere_blobs(n: int, d: int, k: int, sigma: float, seed: int) -> np.ndarray:
     return _redraw_duplicates(x, draw)
 
 
+def uniform_fill(n: int, d: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    side = float(np.sqrt(n))
+    x = (rng.random((n, d)) * side).astype(np.float32)
+    return _redraw_duplicates(x, lambda m: rng.random((m, d)) * side)
+
+
+def gaussian_disc(n: int, d: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    side = 5.0 * float(np.sqrt(n))
+    sigma = float(np.sqrt(n)) / 6.0
+    means = rng.random((5, d)) * side
+    ng = int(round(0.9 * n))
+    lab = np.arange(ng) % 5
+    x = np.empty((n, d))
+    x[:ng] = means[lab] + rng.normal(0.0, sigma, size=(ng, d))
+    x[ng:] = rng.random((n - ng, d)) * side
+    x = x[rng.permutation(n)].astype(np.float32)
+
+    def redraw(m):
+        # a duplicate is redrawn from the uniform part of the law
+        return rng.random((m, d)) * side
+
+    return _redraw_duplicates(x, redraw)
+
+
 # Named workloads. Sizes follow the clustering configurations this library is
 # measured on: a small parity case, 1M and 10M two-dimensional Gaussian
 # mixtures (Ward and complete), 1M ten-dimensional sets (average) and 200K
@@ -98,6 +133,13 @@ WORKLOADS = {
     "u1m_d10": lambda seed=21: uniform(1_000_000, 10, seed),
     "blob100_1m_d10": lambda seed=22: blobs(1_000_000, 10, 100, 0.02, seed),
     "vmf1000_200k_d128": lambda seed=31: sphere_blobs(200_000, 128, 1000, 0.1, seed),
+    # the paper's synthetic sets (Sec. 6), named as in its running-time table
+    "2U1M": lambda seed=61: uniform_fill(1_000_000, 2, seed),
+    "2G1M": lambda seed=62: gaussian_disc(1_000_000, 2, seed),
+    "5U1M": lambda seed=63: uniform_fill(1_000_000, 5, seed),
+    "5G1M": lambda seed=64: gaussian_disc(1_000_000, 5, seed),
+    "2U10M": lambda seed=65: uniform_fill(10_000_000, 2, seed),
+    "2G10M": lambda seed=66: gaussian_disc(10_000_000, 2, seed),
 }
 
 
