@@ -11,7 +11,8 @@ Contents
   * ``canonical``     the dendrogram row convention (sorted rows, scipy ids)
   * ``brute``         generic HAC by brute force, for tiny inputs (``brute.py``)
 
-Linkage codes: 0 complete, 1 average (mean Euclidean), 2 Ward.
+Linkage codes: 0 complete, 1 average (mean Euclidean, avg-1), 2 Ward,
+3 avgsq (mean squared Euclidean, avg-2).
 """
 from __future__ import annotations
 
@@ -29,7 +30,7 @@ _LIB = os.path.join(_LIBDIR, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-LINKAGES = {"complete": 0, "average": 1, "ward": 2}
+LINKAGES = {"complete": 0, "average": 1, "ward": 2, "avgsq": 3}
 
 
 def build(force: bool = False) -> str:

@@ -14,7 +14,7 @@ Ward's distance is taken here from the variance form of Table 1,
 sqrt(2 (Var(A u B) - Var(A) - Var(B))) with Var(S) the sum of squared
 deviations from the mean of S, so it shares no formula with the chain
 oracle's closed form. Complete and average are the max and the mean of the
-explicit pairwise distance matrix.
+explicit pairwise distance matrix, avg-2 the mean of its squares.
 """
 from __future__ import annotations
 
@@ -32,7 +32,10 @@ def delta(x: np.ndarray, A, B, linkage: str) -> float:
     if linkage == "ward":
         v = 2.0 * (_var(np.vstack([PA, PB])) - _var(PA) - _var(PB))
         return float(np.sqrt(max(v, 0.0)))
-    D = np.sqrt(((PA[:, None, :] - PB[None, :, :]) ** 2).sum(axis=2))
+    D2 = ((PA[:, None, :] - PB[None, :, :]) ** 2).sum(axis=2)
+    if linkage == "avgsq":
+        return float(D2.mean())
+    D = np.sqrt(D2)
     if linkage == "complete":
         return float(D.max())
     if linkage == "average":

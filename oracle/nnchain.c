@@ -1,6 +1,7 @@
 /*
  * FP64 reference for hierarchical agglomerative clustering (HAC) under
- * complete, average (mean Euclidean, "avg-1") and Ward linkage.
+ * complete, average (mean Euclidean, "avg-1"), Ward and average with squared
+ * Euclidean distances ("avg-2") linkage.
  *
  * TEST INFRASTRUCTURE ONLY. This file is the oracle that the GPU library is
  * checked against. Nothing in the library links, loads or calls it; only the
@@ -12,6 +13,13 @@
  *       complete  max over x in A, y in B of ||x - y||
  *       average   (1 / (|A||B|)) * sum over x in A, y in B of ||x - y||
  *       Ward      sqrt( 2|A||B| / (|A|+|B|) * ||mean(A) - mean(B)||^2 )
+ *       avg-2     (1 / (|A||B|)) * sum over x in A, y in B of ||x - y||^2,
+ *                 in the chain by its closed form of the same row,
+ *                 ||mean(A) - mean(B)||^2 + Var(A)/|A| + Var(B)/|B|, where
+ *                 Var is the sum of squared deviations from the mean, kept
+ *                 per cluster by the merge rule of Sec. 2.1 (multiplied
+ *                 through by |A|+|B|, see dist_avgsq and the merge step);
+ *                 oracle_linkage evaluates the double sum itself
  *     always in double precision, by direct coordinate differences (never
  *     the ||x||^2 + ||y||^2 - 2 x.y expansion).
  *   * The sequential nearest-neighbour chain algorithm of the introduction:
@@ -46,6 +54,7 @@
 #define ORC_COMPLETE 0
 #define ORC_AVERAGE 1
 #define ORC_WARD 2
+#define ORC_AVGSQ 3
 
 typedef struct {
     int64_t n;
@@ -55,7 +64,8 @@ typedef struct {
     int64_t *head, *tail, *next; /* member list: head[k] -> next[] -> -1 */
     int64_t *size;
     int64_t *node;               /* dendrogram node id of the live cluster */
-    double *sum;                 /* n*d coordinate sums, Ward only */
+    double *sum;                 /* n*d coordinate sums, Ward and avg-2 */
+    double *var;                 /* sum of squared deviations from the mean, avg-2 */
     long long pair_evals;        /* point-pair distance evaluations */
 } orc_state;
 
@@ -111,33 +121,66 @@ static double dist_ward(const orc_state *s, int64_t A, int64_t B)
     return sqrt(w * q);
 }
 
+/* average linkage with squared Euclidean distances (avg-2), closed form of
+ * Table 1 fourth row: ||mean(A) - mean(B)||^2 + Var(A)/|A| + Var(B)/|B|.
+ * The two spread terms are added first, so the value does not depend on
+ * which cluster asks. */
+static double dist_avgsq(const orc_state *s, int64_t A, int64_t B)
+{
+    double na = (double)s->size[A], nb = (double)s->size[B];
+    double q = 0.0;
+    for (int k = 0; k < s->d; ++k) {
+        double t = s->sum[(size_t)A * s->d + k] / na - s->sum[(size_t)B * s->d + k] / nb;
+        q += t * t;
+    }
+    return q + (s->var[A] / na + s->var[B] / nb);
+}
+
 static double dist(const orc_state *s, int linkage, int64_t A, int64_t B)
 {
     switch (linkage) {
     case ORC_COMPLETE: return dist_complete(s, A, B);
     case ORC_AVERAGE: return dist_average(s, A, B);
+    case ORC_AVGSQ: return dist_avgsq(s, A, B);
     default: return dist_ward(s, A, B);
     }
+}
+
+/* Sec. 2.1 merge rule for the spread of A u B, written for Var = sum of
+ * squared deviations (the paper's per-point form times |A|+|B|): the mean
+ * of the union is the size-weighted mean of the two means, and
+ *   Var(A u B) = |A| ||mean(A) - m||^2 + |B| ||mean(B) - m||^2 + Var(A) + Var(B). */
+static double merged_var(const orc_state *s, int64_t A, int64_t B)
+{
+    double na = (double)s->size[A], nb = (double)s->size[B], nu = na + nb;
+    double qa = 0.0, qb = 0.0;
+    for (int k = 0; k < s->d; ++k) {
+        double ma = s->sum[(size_t)A * s->d + k] / na, mb = s->sum[(size_t)B * s->d + k] / nb;
+        double m = (na / nu) * ma + (nb / nu) * mb;
+        qa += (ma - m) * (ma - m);
+        qb += (mb - m) * (mb - m);
+    }
+    return (na * qa + nb * qb) + (s->var[A] + s->var[B]);
 }
 
 /*
  * Sequential NN-chain HAC.
  *   x        n*d float32 points (row-major)
- *   linkage  0 complete, 1 average, 2 Ward
+ *   linkage  0 complete, 1 average, 2 Ward, 3 avg-2
  *   nthreads OpenMP threads for the candidate scan (<=0: runtime default)
  *   out_a/out_b/out_h/out_size  n-1 rows in merge order
  *   cert     optional double[4]: [0] min relative gap (d2-d1)/d2 between the
  *            best and second-best candidate over all queries (1 if none),
  *            [1] number of queries whose best distance is exactly 0,
  *            [2] number of nearest-neighbour queries,
- *            [3] number of point-pair distance evaluations (0 for Ward)
+ *            [3] number of point-pair distance evaluations (0 for Ward, avg-2)
  * Returns 0 on success, -1 on bad arguments, -3 on allocation failure.
  */
 int oracle_nnchain(const float *x, int64_t n, int d, int linkage, int nthreads,
                    int64_t *out_a, int64_t *out_b, double *out_h, int64_t *out_size,
                    double *cert)
 {
-    if (n < 1 || d < 1 || !x || linkage < 0 || linkage > 2) return -1;
+    if (n < 1 || d < 1 || !x || linkage < 0 || linkage > 3) return -1;
     if (n > 1 && (!out_a || !out_b || !out_h || !out_size)) return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -158,11 +201,13 @@ int oracle_nnchain(const float *x, int64_t n, int d, int linkage, int nthreads,
     int64_t *pos = malloc(sizeof(int64_t) * n);   /* ID -> index in act */
     int64_t *chain = malloc(sizeof(int64_t) * n); /* the chain (a stack) */
     double *cand = malloc(sizeof(double) * n);
-    if (linkage == ORC_WARD) s.sum = malloc(sizeof(double) * (size_t)n * d);
+    const int centroids = linkage == ORC_WARD || linkage == ORC_AVGSQ;
+    if (centroids) s.sum = malloc(sizeof(double) * (size_t)n * d);
+    if (linkage == ORC_AVGSQ) s.var = calloc((size_t)n, sizeof(double));
     if (!s.head || !s.tail || !s.next || !s.size || !s.node || !act || !pos || !chain || !cand ||
-        (linkage == ORC_WARD && !s.sum)) {
+        (centroids && !s.sum) || (linkage == ORC_AVGSQ && !s.var)) {
         free(s.head); free(s.tail); free(s.next); free(s.size); free(s.node);
-        free(act); free(pos); free(chain); free(cand); free(s.sum);
+        free(act); free(pos); free(chain); free(cand); free(s.sum); free(s.var);
         return -3;
     }
     for (int64_t i = 0; i < n; ++i) {
@@ -192,7 +237,7 @@ int oracle_nnchain(const float *x, int64_t n, int d, int linkage, int nthreads,
 #pragma omp parallel for schedule(dynamic, 64)
         for (int64_t i = 0; i < nact; ++i)
             cand[i] = (act[i] == a) ? INFINITY : dist(&s, linkage, a, act[i]);
-        if (linkage != ORC_WARD) pairs += (long long)s.size[a] * (long long)(n - s.size[a]);
+        if (!centroids) pairs += (long long)s.size[a] * (long long)(n - s.size[a]);
         queries += 1.0;
         /* argmin over the key (distance, cluster ID); also the runner-up value */
         int64_t b = -1;
@@ -221,7 +266,9 @@ int oracle_nnchain(const float *x, int64_t n, int d, int linkage, int nthreads,
             out_b[nmerge] = s.node[a] < s.node[b] ? s.node[b] : s.node[a];
             out_h[nmerge] = bd;
             out_size[nmerge] = s.size[a] + s.size[b];
-            /* members of hi appended to lo; sums added */
+            /* members of hi appended to lo; spreads merged (from the old
+               means), then sums added */
+            if (s.var) s.var[lo] = merged_var(&s, lo, hi);
             s.next[s.tail[lo]] = s.head[hi];
             s.tail[lo] = s.tail[hi];
             s.size[lo] += s.size[hi];
@@ -245,13 +292,14 @@ int oracle_nnchain(const float *x, int64_t n, int d, int linkage, int nthreads,
         cert[3] = (double)pairs;
     }
     free(s.head); free(s.tail); free(s.next); free(s.size); free(s.node);
-    free(act); free(pos); free(chain); free(cand); free(s.sum);
+    free(act); free(pos); free(chain); free(cand); free(s.sum); free(s.var);
     return 0;
 }
 
 /*
  * Linkage distance between two explicit member sets, from the Table 1
- * definitions (Ward: centroids from FP64 sums taken in member order).
+ * definitions (Ward: centroids from FP64 sums taken in member order; avg-2:
+ * the double sum of squared distances, not its closed form).
  * Returns NAN on bad arguments.
  */
 double oracle_linkage(const float *x, int d, int linkage, const int64_t *A, int64_t na,
@@ -279,11 +327,12 @@ double oracle_linkage(const float *x, int d, int linkage, const int64_t *A, int6
             }
         return sqrt(m);
     }
-    if (linkage == ORC_AVERAGE) {
+    if (linkage == ORC_AVERAGE || linkage == ORC_AVGSQ) {
         double sum = 0.0, c = 0.0;
         for (int64_t i = 0; i < na; ++i)
             for (int64_t j = 0; j < nb; ++j) {
-                double v = sqrt(sq_dist(x, d, A[i], B[j]));
+                double v = sq_dist(x, d, A[i], B[j]);
+                if (linkage == ORC_AVERAGE) v = sqrt(v);
                 double t = sum + v;
                 if (fabs(sum) >= fabs(v)) c += (sum - t) + v;
                 else c += (v - t) + sum;

@@ -1,9 +1,11 @@
 """Pins for the FP64 oracle: it is checked against things other than itself.
 
-* brute-force generic HAC (a different algorithm, a different Ward formula);
-* scipy's ``linkage`` (a library routine with the same height conventions);
+* brute-force generic HAC (a different algorithm, a different Ward formula,
+  avg-2 from its double-sum definition);
+* scipy's ``linkage`` (a library routine with the same height conventions;
+  avg-2 is its average method over squared Euclidean distances);
 * hand-computed values of a six-point instance shaped after the paper's
-  worked example (Sec. 1, Fig. 1);
+  worked example (Sec. 1, Fig. 1), and of two small avg-2 instances;
 * closed forms: two far-apart blobs, n = 2, duplicates, collinear points;
 * the Lance-Williams recurrences of Table 2 (Ward on squared distances);
 * reducibility (Sec. 2.1): heights never decrease from child to parent;
@@ -19,7 +21,7 @@ import synth
 from oracle import brute
 from tests import _trees
 
-LINKS = ["complete", "average", "ward"]
+LINKS = ["complete", "average", "ward", "avgsq"]
 
 
 def _tie_free(x, link):
@@ -60,10 +62,15 @@ def test_nnchain_generic_hac_blobs(link):
 def test_nnchain_matches_scipy(link, n, d, seed):
     from scipy.cluster.hierarchy import linkage
 
+    from scipy.spatial.distance import pdist
+
     x = synth.uniform(n, d, seed)
     Z, cert = oracle.nnchain(x, link, threads=4)
     assert cert["min_gap"] > 1e-12
-    S = linkage(x.astype(np.float64), method=link)
+    if link == "avgsq":
+        S = linkage(pdist(x.astype(np.float64), "sqeuclidean"), method="average")
+    else:
+        S = linkage(x.astype(np.float64), method=link)
     assert _trees.same_tree(Z, S, n, rtol=1e-9)
     _trees.assert_valid(oracle.canonical(Z, n), n)
 
@@ -109,7 +116,7 @@ def test_special_cases():
     x2 = np.array([[0, 0], [3, 4]], np.float32)
     for link in LINKS:
         Z, _ = oracle.nnchain(x2, link)
-        assert Z.shape == (1, 4) and Z[0, 2] == 5.0 and Z[0, 3] == 2
+        assert Z.shape == (1, 4) and Z[0, 2] == (25.0 if link == "avgsq" else 5.0) and Z[0, 3] == 2
     # a duplicated point merges first, at height 0
     x = synth.uniform(20, 2, 5)
     x[7] = x[3]
@@ -140,6 +147,7 @@ def test_two_far_blobs_closed_form(link):
     want = {
         "complete": D.max(),
         "average": D.mean(),
+        "avgsq": (D * D).mean(),
         "ward": math.sqrt(2 * 40 * 25 / 65) * np.linalg.norm(P.mean(0) - Q.mean(0)),
     }[link]
     assert C[-1, 2] == pytest.approx(want, rel=1e-12)
@@ -155,7 +163,7 @@ def test_ward_closed_form_equals_variance_form():
         A, B = p[:a], p[a : a + b]
         assert oracle.linkage_dist(x, "ward", A, B) == pytest.approx(
             brute.delta(x, A, B, "ward"), rel=1e-9)
-        for link in ("complete", "average"):
+        for link in ("complete", "average", "avgsq"):
             assert oracle.linkage_dist(x, link, A, B) == pytest.approx(
                 brute.delta(x, A, B, link), rel=1e-12)
 
@@ -173,8 +181,9 @@ def test_lance_williams_recurrences():
                  oracle.linkage_dist(x, k, B, C), oracle.linkage_dist(x, k, A, B)) for k in LINKS}
         dabc, dac, dbc, dab = D["complete"]
         assert dabc == pytest.approx(0.5 * dac + 0.5 * dbc + 0.5 * abs(dac - dbc), rel=1e-12)
-        dabc, dac, dbc, dab = D["average"]
-        assert dabc == pytest.approx((a * dac + b * dbc) / (a + b), rel=1e-10)
+        for k in ("average", "avgsq"):
+            dabc, dac, dbc, dab = D[k]
+            assert dabc == pytest.approx((a * dac + b * dbc) / (a + b), rel=1e-10)
         dabc, dac, dbc, dab = D["ward"]
         s = a + b + c
         lw = ((a + c) * dac**2 + (b + c) * dbc**2 - c * dab**2) / s
@@ -232,7 +241,7 @@ def test_relabel_and_translation_invariance(link):
     S0 = {frozenset(m): None for m in mem0[n:]}
     assert set(S) == set(S0)
     Zt, _ = oracle.nnchain(x + np.float32(8.0), link)
-    assert _trees.same_tree(Z, Zt, n, rtol=1e-12 if link != "average" else 1e-10)
+    assert _trees.same_tree(Z, Zt, n, rtol=1e-12 if link in ("complete", "ward") else 1e-10)
 
 
 def test_canonical_row_convention():
@@ -277,3 +286,57 @@ def test_spread_identities_used_by_bounds():
         avg = oracle.linkage_dist(x, "average", p[:a], p[a : a + b])
         assert comp * comp >= closed * (1 - 1e-12)
         assert avg <= np.sqrt(closed) * (1 + 1e-12)
+
+
+def _avgsq_instances():
+    out, cur = [], None
+    with open(__file__.replace("test_oracle.py", "golden/avgsq_hand.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            kind, rest = line.split(None, 1)
+            if kind == "instance":
+                name, d = rest.split()
+                cur = {"name": name, "d": int(d), "points": [], "merges": []}
+                out.append(cur)
+            elif kind == "point":
+                cur["points"].append([float(v) for v in rest.split()])
+            else:
+                a, b, h = [t.strip() for t in rest.split("|")]
+                num, _, den = h.partition("/")
+                cur["merges"].append(([int(v) for v in a.split(",")], [int(v) for v in b.split(",")],
+                                      float(num) / float(den or 1)))
+    return out
+
+
+def test_avgsq_hand_computed_instances():
+    """avg-2 merge heights worked out by hand from the double-sum definition."""
+    insts = _avgsq_instances()
+    assert [i["name"] for i in insts] == ["line", "plane"]
+    for inst in insts:
+        x = np.array(inst["points"], np.float32).reshape(-1, inst["d"])
+        n = x.shape[0]
+        Z, _ = oracle.nnchain(x, "avgsq")
+        got = _trees.heights_by_merge(Z, n)
+        assert len(got) == len(inst["merges"]) == n - 1
+        for A, B, h in inst["merges"]:
+            key = tuple(sorted([(min(A), len(A)), (min(B), len(B))]))
+            assert key in got and got[key] == pytest.approx(h, rel=1e-15), (inst["name"], A, B)
+            assert oracle.linkage_dist(x, "avgsq", A, B) == pytest.approx(h, rel=1e-15)
+            assert brute.delta(x, A, B, "avgsq") == pytest.approx(h, rel=1e-15)
+
+
+@pytest.mark.parametrize("d", [2, 7])
+def test_avgsq_closed_form_tracks_definition_at_every_merge(d):
+    """The chain's avg-2 heights come from centroids and spreads carried
+    through every merge (closed form, Sec. 2.1 merge rule); each must equal
+    the double-sum definition over the two children's member sets."""
+    x = synth.blobs(160, d, 6, 0.05, 21 + d)
+    n = x.shape[0]
+    Z, _ = oracle.nnchain(x, "avgsq")
+    mem = oracle.members(Z, n)
+    for r in range(n - 1):
+        A, B = mem[int(Z[r, 0])], mem[int(Z[r, 1])]
+        want = oracle.linkage_dist(x, "avgsq", np.asarray(A), np.asarray(B))
+        assert Z[r, 2] == pytest.approx(want, rel=1e-11, abs=1e-300), r
