@@ -43,7 +43,9 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0
 #   complete tiles: 6 FP64 flops per point pair at d = 2 (2 sub, 2 mul, 1 add,
 #   1 max), priced against the FP64 vector peak.
 def visit_bytes(link, d=2):
-    return 16 + 8 * d + (0 if link == "ward" else 8 * d)
+    # meta (slot, size, cid, spread) + FP64 centroid; avg-2 adds its spread
+    # term, complete/average the FP32 box
+    return 16 + 8 * d + {"ward": 0, "avgsq": 8}.get(link, 8 * d)
 
 
 COMPLETE_PAIR_FLOPS = 6
@@ -149,6 +151,8 @@ PAPER_48H_S = {
     ("2G10M", "complete"): 21.29,
     ("2U1M", "average"): 23.59, ("2G1M", "average"): 26.83, ("5U1M", "average"): 38.10,
     ("5G1M", "average"): 45.27,
+    ("2U1M", "avgsq"): 0.47, ("2G1M", "avgsq"): 0.49, ("5U1M", "avgsq"): 1.65, ("5G1M", "avgsq"): 2.27,
+    ("2U10M", "avgsq"): 5.30, ("2G10M", "avgsq"): 4.80,
 }
 
 
@@ -381,7 +385,8 @@ def main():
     if not args.no_extra and args.workload == "blob50_1m_d2":
         out["workloads"] = {}
         for wl, link in (("u1m_d10", "average"), ("vmf1000_200k_d128", "ward"),
-                         ("vmf1000_200k_d128", "complete"), ("vmf1000_200k_d128", "average")):
+                         ("vmf1000_200k_d128", "complete"), ("vmf1000_200k_d128", "average"),
+                         ("vmf1000_200k_d128", "avgsq")):
             try:
                 out["workloads"]["%s_%s" % (wl, link)] = workload_leg(pc, synth, torch, ctx, stream, wl, link)
             except Exception as e:  # reported, never hidden

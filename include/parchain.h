@@ -40,11 +40,15 @@ typedef enum {
     PC_ERR_CANCELLED = -7
 } pc_status;
 
-/* Linkage criteria of Table 1 (Euclidean distances). */
+/* Linkage criteria of Table 1. */
 typedef enum {
-    PC_LINK_COMPLETE = 0, /* max over x in A, y in B of ||x-y|| */
-    PC_LINK_AVERAGE = 1,  /* "avg-1": mean over x in A, y in B of ||x-y|| */
-    PC_LINK_WARD = 2      /* sqrt(2|A||B|/(|A|+|B|)) * ||mean(A)-mean(B)|| */
+    PC_LINK_COMPLETE = 0,  /* max over x in A, y in B of ||x-y|| */
+    PC_LINK_AVERAGE = 1,   /* "avg-1": mean over x in A, y in B of ||x-y|| */
+    PC_LINK_WARD = 2,      /* sqrt(2|A||B|/(|A|+|B|)) * ||mean(A)-mean(B)|| */
+    PC_LINK_AVERAGE_SQ = 3 /* "avg-2": mean over x in A, y in B of ||x-y||^2
+                              = ||mean(A)-mean(B)||^2 + Var(A)/|A| + Var(B)/|B|
+                              with Var the sum of squared deviations from the
+                              mean; heights are in squared units */
 } pc_linkage;
 
 typedef enum {

@@ -49,7 +49,8 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
               float **xin = nullptr, pc_merge **rows_out = nullptr) {
   Carver c{base};
   const size_t n = (size_t)n64;
-  const bool pts = linkage != kWard;
+  const bool pts = !centroid_link(linkage);
+  const bool avgsq = linkage == kAvgSq;
   S.cid = c.take<int>(n);
   S.csize = c.take<int>(n);
   S.node = c.take<int>(n);
@@ -73,7 +74,8 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   const bool comp = linkage == kComplete;
   S.ext = c.take<int>(comp && d <= kExtMaxDim ? n * 2 * d : 1);
   S.crad = c.take<double>(pts ? n : 1);  // radius bounds: complete and average
-  S.cvar = c.take<double>(pts ? n : 1);
+  S.cvar = c.take<double>(linkage != kWard ? n : 1);
+  S.cmv = c.take<double>(avgsq ? n : 1);
   S.sup = c.take<int>(comp && d == 2 ? n * kSupDirs : 1);
   S.act = c.take<int>(n);
   S.act2 = c.take<int>(n);
@@ -92,6 +94,7 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   S.item_slot = c.take<int>(grid ? n : 1);
   S.item_meta = c.take<int4>(grid ? n : 1);
   S.item_cen = c.take<double>(grid ? n * d : 1);
+  S.item_v = c.take<double>(grid && avgsq ? n : 1);
   S.item_lo = c.take<float>(grid && pts ? n * d : 1);
   S.item_hi = c.take<float>(grid && pts ? n * d : 1);
   const bool gram = d >= kGramMinDim && d <= kGramMaxDim;
@@ -242,16 +245,16 @@ void pc_context_destroy(pc_context *c) {
 }
 
 size_t pc_hac_workspace_bytes(int64_t n, int32_t d, int32_t linkage, const pc_options *opt) {
-  if (n < 1 || d < 1 || d > kMaxDim || n > 2147483646LL || linkage < 0 || linkage > 2) return 0;
+  if (n < 1 || d < 1 || d > kMaxDim || n > 2147483646LL || linkage < 0 || linkage > 3) return 0;
   State S;
   size_t bytes = layout(S, nullptr, n, d, linkage, true);
   const bool gram = d >= kGramMinDim && d <= kGramMaxDim;
   // initial candidate record (grown on demand), pair list, tiles and filter
   const size_t cand = (size_t)std::max<int64_t>(1 << 22, 4 * n);
   const size_t per_cand = 2 * sizeof(double) + sizeof(long long) + sizeof(int4) + 4 * sizeof(int);
-  if (linkage != kWard || gram) bytes += cand * per_cand + 1024;
+  if (!centroid_link(linkage) || gram) bytes += cand * per_cand + 1024;
   bytes += ((size_t)(2 * n + 64) / 1024 + 1024) * sizeof(long long);
-  if (linkage != kWard) {
+  if (!centroid_link(linkage)) {
     const size_t pc = (size_t)std::max<int64_t>(1 << 20, 2 * n);
     bytes += pc * (4 * sizeof(long long) + 6 * sizeof(int)) + 1024;
     if (linkage == kAverage) bytes += ((size_t)1 << 22) * sizeof(double);
@@ -344,14 +347,14 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   if (n < 1) return fail(PC_ERR_INVALID_ARG, "n must be >= 1");
   if (n > 2147483646LL) return fail(PC_ERR_INVALID_ARG, "n must be <= 2^31-2");
   if (d < 1 || d > kMaxDim) return fail(PC_ERR_INVALID_ARG, "d must be in [1, 2048]");
-  if (linkage < 0 || linkage > 2) return fail(PC_ERR_INVALID_ARG, "unknown linkage");
+  if (linkage < 0 || linkage > 3) return fail(PC_ERR_INVALID_ARG, "unknown linkage");
   if (n > 1 && !out) return fail(PC_ERR_INVALID_ARG, "out is NULL");
   if (opt && opt->struct_size != sizeof(pc_options)) return fail(PC_ERR_INVALID_ARG, "pc_options.struct_size");
   if (stats && stats->struct_size != sizeof(pc_stats)) return fail(PC_ERR_INVALID_ARG, "pc_stats.struct_size");
   const int prune = opt ? (opt->prune != 0) : 1;
   int cache_slots = opt ? opt->cache_slots : -1;
   if (cache_slots < 0) cache_slots = linkage == kAverage ? 64 : 0;
-  if (linkage == kWard) cache_slots = 0;  // Ward distances cost less than a probe
+  if (centroid_link(linkage)) cache_slots = 0;  // Ward / avg-2 values cost less than a probe
   if (opt && opt->precision != PC_PREC_EXACT) return fail(PC_ERR_UNSUPPORTED, "precision mode not available");
   if (!points_on_device) {
     for (int64_t i = 0; i < n * (int64_t)d; ++i)
@@ -388,9 +391,9 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   S.linkage = linkage;
   S.prune = prune;
   S.timing = (opt && opt->timing) ? 1 : 0;
-  // Ward keeps the centroid grid through d = 5 (measured faster there than
-  // the Gram search on 1M-point 5-D sets); tuning knob PC_GRAM_MIN_DIM
-  int gram_min = linkage == kWard ? 6 : kGramMinDim;
+  // Ward and avg-2 keep the centroid grid through d = 5 (measured faster
+  // there than the Gram search on 1M-point 5-D sets); tuning knob PC_GRAM_MIN_DIM
+  int gram_min = centroid_link(linkage) ? 6 : kGramMinDim;
   if (const char *e = getenv("PC_GRAM_MIN_DIM")) gram_min = std::max(kGramMinDim, atoi(e));
   S.gram = (prune && d >= gram_min && d <= kGramMaxDim) ? 1 : 0;
   S.tev = ctx->tev;
@@ -420,12 +423,12 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     pc_status st = grow_part(ctx, S, 2LL * n + 64);
     if (st != PC_OK) return st;
   }
-  if (linkage == kWard && S.gram) {
+  if (centroid_link(linkage) && S.gram) {
     pc_status st = grow_cand(ctx, S, std::max<long long>(1 << 22, 4 * n));
     if (st != PC_OK) return st;
     if (const char *e = getenv("PC_TEST_CAND_CAP")) S.cand_cap = std::min<long long>(S.cand_cap, atoll(e));
   }
-  if (linkage != kWard) {
+  if (!centroid_link(linkage)) {
     pc_status st = grow_pairs(ctx, S, std::max<long long>(1 << 20, 2 * n));
     if (st != PC_OK) return st;
     st = grow_tiles(ctx, S, linkage == kAverage ? (1 << 22) : 1);
@@ -475,7 +478,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   const bool debug = getenv("PC_DEBUG") != nullptr;
   // tuning knob: cells a thread-per-terminal ring search visits before it
   // hands the terminal to the block search
-  S.cell_budget = linkage == kWard ? 24 : 160;  // measured on the 1M 2-D workload
+  S.cell_budget = centroid_link(linkage) ? 24 : 160;  // measured on the 1M 2-D workload
   if (const char *e = getenv("PC_CELL_BUDGET")) S.cell_budget = std::max(1, atoi(e));
   long long gram_batch = 0;  // terminals per Gram batch (0: all), kept across rounds
   // test hook: small batches exercise the batch loop on small inputs
@@ -587,7 +590,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
           }
           continue;
         }
-        if (linkage == kWard) {
+        if (centroid_link(linkage)) {
           launch_gram_keys(S, s);
         } else {
           bool too_big = false;

@@ -33,7 +33,12 @@ inline int gram_kp(int d) {
 }
 constexpr uint32_t kInfBits = 0x7f800000u;
 
-enum Linkage { kComplete = 0, kAverage = 1, kWard = 2 };
+// avg-1 is the mean Euclidean distance, avg-2 the mean squared distance
+enum Linkage { kComplete = 0, kAverage = 1, kWard = 2, kAvgSq = 3 };
+
+// Ward and avg-2 values follow from centroids, sizes (and for avg-2 the
+// spreads) alone, in O(1) (Table 1); these linkages keep no points.
+__host__ __device__ constexpr bool centroid_link(int l) { return l == kWard || l == kAvgSq; }
 
 // ---------------------------------------------------------------- helpers --
 // Reserve one slot of a 64-bit append counter; returns the slot index.
@@ -138,7 +143,8 @@ struct State {
   float *lo, *hi;  // d-dimensional bounding box per slot (complete, average)
   int *ext;        // complete: 2d original point indices attaining the box faces (lo_k, hi_k)
   double *crad;    // complete, average: upper bound of the largest centroid-to-point distance
-  double *cvar;    // complete, average: sum of squared deviations from the centroid (FP64)
+  double *cvar;    // complete, average, avg-2: sum of squared deviations from the centroid (FP64)
+  double *cmv;     // avg-2: cvar / size, the spread term of the linkage value
   int *sup;        // complete, d == 2: kSupDirs original point indices, the cluster's
                    // support point in direction (cos, sin)(2 pi k / kSupDirs)
   const float *xin;  // the caller's points (original order)
@@ -150,6 +156,7 @@ struct State {
   int *item_slot;
   int4 *item_meta;    // (slot, size, cid, 0)
   double *item_cen;   // d per item
+  double *item_v;     // avg-2: the cluster's spread term (cmv)
   float *item_lo, *item_hi;
   // per terminal
   double *t_best;                 // value of the best inline candidate

@@ -206,17 +206,16 @@ __global__ void k_init_slots(State S, const float *x, const unsigned *perm) {
     S.wsum[(size_t)s * d + k] = (double)v;
     S.wcen[(size_t)s * d + k] = (double)v;
   }
-  if (S.linkage != kWard) {
-    S.crad[s] = 0.0;
-    S.cvar[s] = 0.0;
-  }
+  if (!centroid_link(S.linkage)) S.crad[s] = 0.0;
+  if (S.linkage != kWard) S.cvar[s] = 0.0;
+  if (S.linkage == kAvgSq) S.cmv[s] = 0.0;
   if (S.linkage == kComplete) {
     if (d == 2)
       for (int k = 0; k < kSupDirs; ++k) S.sup[(size_t)s * kSupDirs + k] = p;
     if (d <= kExtMaxDim)
       for (int k = 0; k < 2 * d; ++k) S.ext[(size_t)s * 2 * d + k] = p;
   }
-  if (S.linkage != kWard) {
+  if (!centroid_link(S.linkage)) {
     S.cbeg[s] = s;
     S.powner[s] = s;
     for (int k = 0; k < d; ++k) {
@@ -377,7 +376,8 @@ __global__ void k_cell_scatter(State S) {
     S.item_slot[pos] = s;
     S.item_meta[pos] = make_int4(s, S.csize[s], S.cid[s], S.linkage == kComplete ? spread_bits(spread_lo(S, s)) : 0);
     for (int k = 0; k < d; ++k) S.item_cen[(size_t)pos * d + k] = S.wcen[(size_t)s * d + k];
-    if (S.linkage != kWard)
+    if (S.linkage == kAvgSq) S.item_v[pos] = S.cmv[s];
+    if (!centroid_link(S.linkage))
       for (int k = 0; k < d; ++k) {
         S.item_lo[(size_t)pos * d + k] = S.lo[(size_t)s * d + k];
         S.item_hi[(size_t)pos * d + k] = S.hi[(size_t)s * d + k];
@@ -406,6 +406,36 @@ __device__ __forceinline__ double ward_key(const double *ct, double nt, const do
   }
   const double w = (2.0 * nt * nc) / (nt + nc);
   return w * q;
+}
+
+// avg-2 key: ||cA - cB||^2 + (Var(A)/|A| + Var(B)/|B|) (Table 1, the mean
+// squared point distance), v = Var/|.| per cluster. The two spread terms are
+// added first, so the value does not depend on which side asks.
+template <int MAXD>
+__device__ __forceinline__ double avgsq_key(const double *ct, double vt, const double *cc, double vc, int d) {
+  double q = 0.0;
+  if (MAXD > 0) {
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k)
+      if (k < d) {
+        double t = ct[k] - cc[k];
+        q += t * t;
+      }
+  } else {
+    for (int k = 0; k < d; ++k) {
+      double t = ct[k] - cc[k];
+      q += t * t;
+    }
+  }
+  return q + (vt + vc);
+}
+
+// Key of a centroid linkage (Ward: sizes; avg-2: spread terms).
+template <int LINK, int MAXD>
+__device__ __forceinline__ double cen_key(const double *ct, double nt, double vt, const double *cc, double nc,
+                                          double vc, int d) {
+  if (LINK == kWard) return ward_key<MAXD>(ct, nt, cc, nc, d);
+  return avgsq_key<MAXD>(ct, vt, cc, vc, d);
 }
 
 // Exact complete (largest squared distance) or average (mean distance) value
@@ -762,6 +792,7 @@ template <int LINK>
 __device__ __forceinline__ double ring_key_lb(double D, double nt, double nmin) {
   if (LINK == kWard) return D * D * ((2.0 * nt * nmin) / (nt + nmin));  // Sec. 4.1 radius
   if (LINK == kComplete) return D * D;  // Sec. 4.3: centroid distance <= complete distance
+  if (LINK == kAvgSq) return D * D;     // Sec. 4.2: squared centroid distance <= avg-2 (+ spreads)
   return D;                             // Sec. 4.2: centroid distance <= average distance
 }
 
@@ -770,11 +801,15 @@ template <int LINK>
 __device__ __forceinline__ double beta_key(unsigned predbits) {
   if (predbits >= kInfBits) return INFINITY;
   double b = (double)__uint_as_float(predbits);
-  if (LINK == kAverage) return b * kSlack;
+  if (LINK == kAverage || LINK == kAvgSq) return b * kSlack;
   return b * b * kSlack;
 }
 
-__device__ __forceinline__ double key_to_height(int link, double v) { return link == kAverage ? v : sqrt(v); }
+// Heights: complete and Ward keys are squared distances; average and avg-2
+// keys are the heights themselves.
+__device__ __forceinline__ double key_to_height(int link, double v) {
+  return (link == kAverage || link == kAvgSq) ? v : sqrt(v);
+}
 
 // ------------------------------------------------------ ring search kernel --
 // One thread per terminal. PASS 0: Ward (final result) or, for complete and
@@ -798,13 +833,16 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
 #pragma unroll
     for (int k = 0; k < MAXD; ++k) {
       ct[k] = k < d ? S.wcen[(size_t)t * d + k] : 0.0;
-      if (LINK != kWard) {
+      if (!centroid_link(LINK)) {
         lt[k] = k < d ? S.lo[(size_t)t * d + k] : 0.f;
         ht[k] = k < d ? S.hi[(size_t)t * d + k] : 0.f;
       }
     }
-    const int beg_t = LINK != kWard ? S.cbeg[t] : 0;
-    const double sp_t = LINK == kComplete ? spread_lo(S, t) : 0.0;
+    const int beg_t = !centroid_link(LINK) ? S.cbeg[t] : 0;
+    const double vt = LINK == kAvgSq ? S.cmv[t] : 0.0;
+    // complete: own spread (lowered); avg-2: own spread term (exact, every
+    // key is at least the squared centroid distance plus it)
+    const double sp_t = LINK == kComplete ? spread_lo(S, t) : vt;
     bool skip = false;
     double bound;
     double bestv = INFINITY;
@@ -876,11 +914,12 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
               if (s == t) continue;
               const double *cc = S.item_cen + (size_t)it * d;
               const unsigned long long key = make_key(mt.z, s);
-              if (LINK == kWard) {
+              if (centroid_link(LINK)) {
                 double cv[MAXD];
 #pragma unroll
                 for (int q = 0; q < MAXD; ++q) cv[q] = q < d ? cc[q] : 0.0;
-                const double v = ward_key<MAXD>(ct, nt, cv, (double)mt.y, d);
+                const double v =
+                    cen_key<LINK, MAXD>(ct, nt, vt, cv, (double)mt.y, LINK == kAvgSq ? S.item_v[it] : 0.0, d);
                 ++evals;
                 if (v <= bound && better(v, key, bestv, bestk)) {
                   bestv = v;
@@ -985,7 +1024,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
           S.ovf[o] = ti;
         } else {
           t_ovf[ti] = 0;
-          if (LINK == kWard && bestk == kNoKey) {
+          if (centroid_link(LINK) && bestk == kNoKey) {
             // the predecessor bound was not met (cannot happen for an exact
             // bound); hand the terminal to the full scan without a bound
             t_ovf[ti] = 1;
@@ -994,7 +1033,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
           } else {
             S.t_best[ti] = bestv;
             S.t_key[ti] = bestk;
-            if (LINK != kWard) {
+            if (!centroid_link(LINK)) {
               S.t_beta[ti] = fmin(bound, bestv);
               S.t_min[ti] = pos_bits(bestv);
             }
@@ -1069,7 +1108,7 @@ __device__ __forceinline__ double cell_key_lb(double D, double nt, int cnmin) {
     const double nm = (double)cnmin;
     return D * D * ((2.0 * nt * nm) / (nt + nm));
   }
-  if (LINK == kComplete) return D * D;
+  if (LINK == kComplete || LINK == kAvgSq) return D * D;
   return D;
 }
 
@@ -1095,17 +1134,18 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
 #pragma unroll
     for (int k = 0; k < MAXD; ++k) {
       ct[k] = k < d ? S.wcen[(size_t)t * d + k] : 0.0;
-      lt[k] = (LINK != kWard && k < d) ? S.lo[(size_t)t * d + k] : 0.f;
-      ht[k] = (LINK != kWard && k < d) ? S.hi[(size_t)t * d + k] : 0.f;
+      lt[k] = (!centroid_link(LINK) && k < d) ? S.lo[(size_t)t * d + k] : 0.f;
+      ht[k] = (!centroid_link(LINK) && k < d) ? S.hi[(size_t)t * d + k] : 0.f;
     }
-    const int beg_t = LINK != kWard ? S.cbeg[t] : 0;
-    const double sp_t = LINK == kComplete ? spread_lo(S, t) : 0.0;
+    const int beg_t = !centroid_link(LINK) ? S.cbeg[t] : 0;
+    const double vt = LINK == kAvgSq ? S.cmv[t] : 0.0;
+    const double sp_t = LINK == kComplete ? spread_lo(S, t) : vt;
     const int cx = cell_coord(ct[0], g.org[0], g.inv_h, g.G[0]);
     const int cy = g.axes == 2 ? cell_coord(ct[1], g.org[1], g.inv_h, g.G[1]) : 0;
     const int kmax = max(max(cx, g.G[0] - 1 - cx), max(cy, g.G[1] - 1 - cy));
     double beta_final = 0.0;
     bool use_pred = true;
-    for (int pass = 0; pass < (LINK == kWard ? 1 : 2); ++pass) {
+    for (int pass = 0; pass < (centroid_link(LINK) ? 1 : 2); ++pass) {
       double bound = pass == 0 ? (use_pred ? beta_key<LINK>(S.predd[t]) : INFINITY) : beta_final * kSlack;
       double bestv = INFINITY;
       unsigned long long bestk = kNoKey;
@@ -1160,8 +1200,9 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
             double cv[MAXD];
 #pragma unroll
             for (int q = 0; q < MAXD; ++q) cv[q] = q < d ? cc[q] : 0.0;
-            if (LINK == kWard) {
-              const double v = ward_key<MAXD>(ct, nt, cv, (double)mt.y, d);
+            if (centroid_link(LINK)) {
+              const double v =
+                  cen_key<LINK, MAXD>(ct, nt, vt, cv, (double)mt.y, LINK == kAvgSq ? S.item_v[it] : 0.0, d);
               ++evals;
               if (v <= bound && better(v, key, bestv, bestk)) {
                 bestv = v;
@@ -1287,7 +1328,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
           if (ring_key_lb<LINK>(D, nt, (double)S.cnt->n_min) + sp_t > cur) break;
         }
       }
-      if (LINK == kWard && pass == 0 && bestk == kNoKey && use_pred) {
+      if (centroid_link(LINK) && pass == 0 && bestk == kNoKey && use_pred) {
         // the predecessor bound held nothing (cannot happen for an exact
         // bound): search again without it
         use_pred = false;
@@ -1300,7 +1341,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
         if (threadIdx.x == 0) {
           S.t_best[ti] = bestv;
           S.t_key[ti] = bestk;
-          if (LINK != kWard) {
+          if (!centroid_link(LINK)) {
             S.t_beta[ti] = beta_final;
             S.t_min[ti] = pos_bits(bestv);
           }
@@ -1339,13 +1380,14 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
     const double nt = (double)n_t;
     for (int k = threadIdx.x; k < d; k += blockDim.x) {
       ct[k] = S.wcen[(size_t)t * d + k];
-      if (LINK != kWard) {
+      if (!centroid_link(LINK)) {
         lt[k] = S.lo[(size_t)t * d + k];
         ht[k] = S.hi[(size_t)t * d + k];
       }
     }
     __syncthreads();
-    const int beg_t = LINK != kWard ? S.cbeg[t] : 0;
+    const int beg_t = !centroid_link(LINK) ? S.cbeg[t] : 0;
+    const double vt = LINK == kAvgSq ? S.cmv[t] : 0.0;
     double bound = S.prune ? beta_key<LINK>(S.predd[t]) : INFINITY;
     double bestv = INFINITY;
     unsigned long long bestk = kNoKey;
@@ -1356,9 +1398,9 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
       const unsigned long long key = make_key(S.cid[s], s);
       const int n_c = S.csize[s];
       const double *cc = S.wcen + (size_t)s * d;
-      if (LINK == kWard) {
-        // a full scan needs no bound for Ward: every candidate is evaluated
-        const double v = ward_key<0>(ct, nt, cc, (double)n_c, d);
+      if (centroid_link(LINK)) {
+        // a full scan needs no bound for Ward / avg-2: every candidate is evaluated
+        const double v = cen_key<LINK, 0>(ct, nt, vt, cc, (double)n_c, LINK == kAvgSq ? S.cmv[s] : 0.0, d);
         ++evals;
         if (better(v, key, bestv, bestk)) {
           bestv = v;
@@ -1431,12 +1473,12 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
     if (threadIdx.x == 0) {
       S.t_best[ti] = bestv;
       S.t_key[ti] = bestk;
-      if (LINK != kWard) {
+      if (!centroid_link(LINK)) {
         S.t_beta[ti] = beta;
         S.t_min[ti] = pos_bits(bestv);
       }
     }
-    if (LINK != kWard) {
+    if (!centroid_link(LINK)) {
       // emit the large pairs that the final bound does not exclude
       for (int i = threadIdx.x; i < nact; i += blockDim.x) {
         const int s = S.act[i];
@@ -2070,7 +2112,7 @@ __global__ void k_gram_reset(State S) {
 // FP16 copy of every active centroid (active-list order, zero beyond d) and
 // its FP32 terms: x = |x~|^2 (+ mean squared spread for complete/average:
 // the bound pass estimate), y = |x~|^2 - e rounded down, z = eta rounded up,
-// w = 1/size (Ward) or the mean squared spread rounded down (complete).
+// w = 1/size (Ward) or the mean squared spread rounded down (complete, avg-2).
 // A wave per item, lanes over dims.
 __global__ void k_gram_prep(State S) {
   const int nact = S.cnt->n_act, d = S.d, kp = S.gkp;
@@ -2141,6 +2183,7 @@ __device__ double gram_pick_upper(const State &S, int t, int c) {
   const int d = S.d;
   const double *ct = S.wcen + (size_t)t * d, *cc = S.wcen + (size_t)c * d;
   if (LINK == kWard) return ward_key<0>(ct, (double)S.csize[t], cc, (double)S.csize[c], d);
+  if (LINK == kAvgSq) return avgsq_key<0>(ct, S.cmv[t], cc, S.cmv[c], d);
   double v;
   if (cache_resolve(S, S.node[t], S.node[c], v)) return v;
   const int nt = S.csize[t], nc = S.csize[c];
@@ -2223,7 +2266,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
         float uf = f32_up(us * (double)kGMargin);
         uf = uf > 1e-30f ? uf : 1e-30f;
         if (LINK == kWard) qthr[r] = 0.5f * uf;
-        else if (LINK == kComplete) qthr[r] = uf - g.w;
+        else if (LINK == kComplete || LINK == kAvgSq) qthr[r] = uf - g.w;
         else qthr[r] = uf + g.z;
       }
     } else {
@@ -2324,7 +2367,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
         const float lhs = __builtin_fmaf(-2.0f, acc[i], rq[i] + cm);
         float rr;
         if (LINK == kWard) rr = __builtin_amdgcn_sqrtf(rt[i] * (rz[i] + cw)) + (re[i] + ce);
-        else if (LINK == kComplete) rr = __builtin_amdgcn_sqrtf(rt[i] - cw) + (re[i] + ce);
+        else if (LINK == kComplete || LINK == kAvgSq) rr = __builtin_amdgcn_sqrtf(rt[i] - cw) + (re[i] + ce);
         else rr = rt[i] + ce;
         rmask |= (lhs <= rr * rr ? 1u : 0u) << i;
       }
@@ -2801,7 +2844,7 @@ __global__ void k_gram_exact(State S) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
     const int ti = S.cd_t[i], c = S.cd_c[i];
     const double lb = S.cd_lb[i];
-    if (LINK != kWard && lb < 0.0) {
+    if (!centroid_link(LINK) && lb < 0.0) {
       // exact value of a small pair, from the triage pass
       atomicMin(&S.t_min[ti], pos_bits(S.cd_v[i]));
       continue;
@@ -2810,8 +2853,9 @@ __global__ void k_gram_exact(State S) {
     if (lb > S.t_beta[ti] * kSlack) continue;
     const int t = S.term[ti];
     double v;
-    if (LINK == kWard) {
-      v = ward_key<0>(S.wcen + (size_t)t * d, (double)S.csize[t], S.wcen + (size_t)c * d, (double)S.csize[c], d);
+    if (centroid_link(LINK)) {
+      v = cen_key<LINK, 0>(S.wcen + (size_t)t * d, (double)S.csize[t], LINK == kAvgSq ? S.cmv[t] : 0.0,
+                           S.wcen + (size_t)c * d, (double)S.csize[c], LINK == kAvgSq ? S.cmv[c] : 0.0, d);
       ++evals;
     } else {
       const int nt = S.csize[t], ncs = S.csize[c];
@@ -2884,7 +2928,7 @@ __global__ void k_chain(State S) {
       continue;
     }
     const int u = (int)(key & 0xffffffffu);
-    const double v = (S.linkage == kWard && !S.gram) ? S.t_best[ti] : pos_from_bits(S.t_min[ti]);
+    const double v = (centroid_link(S.linkage) && !S.gram) ? S.t_best[ti] : pos_from_bits(S.t_min[ti]);
     const double h = key_to_height(S.linkage, v);
     S.succ[t] = u;
     S.succ_node[t] = S.node[u];
@@ -2951,7 +2995,7 @@ __global__ void k_merge(State S, int base) {
     S.eff[a] = e;
     const int ns = sa + sb;
     S.csize[a] = ns;
-    if (S.linkage != kWard) {
+    if (!centroid_link(S.linkage)) {
       // radius bound of the union: max over children of |c_new - c_child| + r_child
       // (old centroids are still in place here)
       double da = 0.0, db = 0.0;
@@ -2963,6 +3007,8 @@ __global__ void k_merge(State S, int base) {
       }
       const double ra = sqrt(da) + S.crad[a], rb = sqrt(db) + S.crad[b];
       S.crad[a] = (ra > rb ? ra : rb) * (1.0 + 1e-12);
+    }
+    if (S.linkage != kWard) {
       // Var(A u B) = Var(A) + Var(B) + |A||B|/(|A|+|B|) |cA - cB|^2 (sums of
       // squared deviations; the merge rule of Sec. 2.1 with its size factor)
       double cab = 0.0;
@@ -2971,6 +3017,7 @@ __global__ void k_merge(State S, int base) {
         cab += t * t;
       }
       S.cvar[a] = S.cvar[a] + S.cvar[b] + ((double)sa * (double)sb / (double)ns) * cab;
+      if (S.linkage == kAvgSq) S.cmv[a] = S.cvar[a] / (double)ns;
     }
     if (S.linkage == kComplete) {
       if (d <= kExtMaxDim)
@@ -2987,7 +3034,7 @@ __global__ void k_merge(State S, int base) {
       S.wsum[(size_t)a * d + k] = sum;
       S.wcen[(size_t)a * d + k] = sum / (double)ns;
     }
-    if (S.linkage != kWard) {
+    if (!centroid_link(S.linkage)) {
       for (int k = 0; k < d; ++k) {
         S.lo[(size_t)a * d + k] = fminf(S.lo[(size_t)a * d + k], S.lo[(size_t)b * d + k]);
         S.hi[(size_t)a * d + k] = fmaxf(S.hi[(size_t)a * d + k], S.hi[(size_t)b * d + k]);
@@ -3185,7 +3232,7 @@ void launch_cand_tiles(State &S, int ncand, hipStream_t s) {
 // values or claims.
 template <int LINK>
 void launch_gram_refine_t(State &S, int ncand, hipStream_t s) {
-  if constexpr (LINK != kWard) {
+  if constexpr (!centroid_link(LINK)) {
     if (!S.p16 || ncand <= 0) goto exact;
     k_cand_triage<LINK><<<nblk(ncand, 4096), kBlock, 0, s>>>(S, ncand);
     k_cand_small<LINK><<<8192, kBlock, 0, s>>>(S);
@@ -3239,6 +3286,7 @@ void launch_gram_keys(State &S, hipStream_t s) { k_gram_key<<<2048, kBlock, 0, s
 void launch_gram_refine(State &S, int ncand, hipStream_t s) {
   switch (S.linkage) {
   case kWard: launch_gram_refine_t<kWard>(S, ncand, s); break;
+  case kAvgSq: launch_gram_refine_t<kAvgSq>(S, ncand, s); break;
   case kComplete: launch_gram_refine_t<kComplete>(S, ncand, s); break;
   default: launch_gram_refine_t<kAverage>(S, ncand, s); break;
   }
@@ -3247,6 +3295,7 @@ void launch_gram_refine(State &S, int ncand, hipStream_t s) {
 void launch_gram_batch(State &S, int nact, hipStream_t s) {
   switch (S.linkage) {
   case kWard: launch_gram_batch_t<kWard>(S, nact, s); break;
+  case kAvgSq: launch_gram_batch_t<kAvgSq>(S, nact, s); break;
   case kComplete: launch_gram_batch_t<kComplete>(S, nact, s); break;
   default: launch_gram_batch_t<kAverage>(S, nact, s); break;
   }
@@ -3321,11 +3370,12 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
     // the host then runs the terminals in batches (launch_gram_batch)
     k_term_pos<<<gb, kBlock, 0, s>>>(S);
     launch_gram_setup(S, nact, s);
-    need_pairs = S.linkage != kWard;
+    need_pairs = !centroid_link(S.linkage);
     return;
   }
   switch (S.linkage) {
   case kWard: launch_search<kWard>(S, nact, s, t_ovf); break;
+  case kAvgSq: launch_search<kAvgSq>(S, nact, s, t_ovf); break;
   case kComplete:
     launch_search<kComplete>(S, nact, s, t_ovf);
     if (S.d <= kGridMaxDim && S.prune) {
@@ -3416,7 +3466,7 @@ void launch_round_tail(State &S, int round, int nact, int merges_before, hipStre
   k_scatter_flagged<<<gb, kBlock, 0, s>>>(S.act, S.flags, S.scan, &S.cnt->n_act, S.act2);
   k_swap_count<<<1, 1, 0, s>>>(S.cnt, total);
   std::swap(S.act, S.act2);
-  if (S.linkage != kWard) {
+  if (!centroid_link(S.linkage)) {
     k_sizes_of_act<<<gb, kBlock, 0, s>>>(S);
     scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, nullptr, S.part, s);
     k_set_nbeg<<<gb, kBlock, 0, s>>>(S);

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libparchain.so")
 
-LINKAGES = {"complete": 0, "average": 1, "ward": 2}
+LINKAGES = {"complete": 0, "average": 1, "ward": 2, "avgsq": 3}
 
 PC_OK = 0
 STATUS = {

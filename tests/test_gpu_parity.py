@@ -5,7 +5,10 @@ Pass criteria (on inputs the oracle certifies tie-free):
   * heights: complete and Ward are computed with the oracle's FP64 formulas
     (inputs widened exactly, no FMA contraction), so they must agree to the
     last bit; average sums point distances in another order, so 1e-12
-    relative (the stated contract is 1e-5);
+    relative (the stated contract is 1e-5); avg-2 shares the centroid term
+    bit for bit but carries each cluster's spread by another (equivalent)
+    merge rule, whose rounding is bounded by a few ulps of |x| / separation
+    per level, so 1e-10 relative;
   * rows in the documented canonical order.
 """
 import numpy as np
@@ -17,8 +20,8 @@ from tests import _trees
 
 pytestmark = pytest.mark.gpu
 
-LINKS = ["complete", "average", "ward"]
-RTOL = {"complete": 0.0, "ward": 0.0, "average": 1e-12}
+LINKS = ["complete", "average", "ward", "avgsq"]
+RTOL = {"complete": 0.0, "ward": 0.0, "average": 1e-12, "avgsq": 1e-10}
 
 
 @pytest.fixture(scope="module")
@@ -92,7 +95,7 @@ def test_parity_c1_complete_2k(pc):
 def test_parity_blobs_20k(pc, link):
     """Gaussian-mixture data shaped like the 1M workload, at a size the oracle
     finishes in seconds; spans many grid rings, overflow scans and tiles."""
-    n = 20_000 if link == "ward" else 6_000
+    n = 20_000 if link in ("ward", "avgsq") else 6_000
     x = synth.blobs(n, 2, 50, 0.01, 11)
     Zg, st, cert = check_parity(pc, x, link)
     assert st["rounds"] > 1
@@ -135,7 +138,7 @@ def test_special_cases(pc):
         Z = pc.hac(np.zeros((1, 3), np.float32), link)
         assert Z.shape == (0, 4)
         Z = pc.hac(np.array([[0, 0], [3, 4]], np.float32), link)
-        assert Z.shape == (1, 4) and Z[0, 2] == 5.0 and Z[0, 3] == 2
+        assert Z.shape == (1, 4) and Z[0, 2] == (25.0 if link == "avgsq" else 5.0) and Z[0, 3] == 2
         x = synth.uniform(50, 2, 5)
         x[7] = x[3]
         Z = pc.hac(x, link)
@@ -262,3 +265,40 @@ def test_interval_screening(pc, link, d):
     assert _trees.same_tree(Zg, Zo, n, rtol=RTOL[link])
     Z0 = pc.hac(x, link, cache_slots=0)
     assert same_rows(Zg, Z0, link)
+
+
+def test_avgsq_hand_computed_instances(pc):
+    """avg-2 heights worked out by hand from the double-sum definition (the
+    oracle's own pin), now from the GPU path."""
+    from tests.test_oracle import _avgsq_instances
+
+    for inst in _avgsq_instances():
+        x = np.array(inst["points"], np.float32).reshape(-1, inst["d"])
+        n = x.shape[0]
+        got = _trees.heights_by_merge(pc.hac(x, "avgsq"), n)
+        for A, B, h in inst["merges"]:
+            key = tuple(sorted([(min(A), len(A)), (min(B), len(B))]))
+            assert got[key] == pytest.approx(h, rel=1e-15), (inst["name"], A, B)
+
+
+@pytest.mark.parametrize("d", [2, 3, 5])
+def test_avgsq_ring_handoff(pc, d, monkeypatch):
+    """avg-2 on the centroid grid: a one-cell budget hands every terminal to
+    the block ring search; rows must not change."""
+    x = synth.blobs(8000, d, 40, 0.01, 70 + d)
+    Z0 = pc.hac(x, "avgsq")
+    monkeypatch.setenv("PC_CELL_BUDGET", "1")
+    Z1, st = pc.hac(x, "avgsq", return_stats=True)
+    assert np.array_equal(Z0, Z1) and st["overflow_queries"] > 0
+    Zo, _ = oracle.nnchain(x, "avgsq", threads=8)
+    assert _trees.same_tree(Z0, Zo, 8000, rtol=RTOL["avgsq"])
+
+
+def test_avgsq_gram_from_dim_four(pc, monkeypatch):
+    """The Gram search serves avg-2 from d = 6 by default; forced down to
+    d = 4 it must give the grid's rows."""
+    x = synth.blobs(3000, 4, 25, 0.02, 75)
+    Z0 = pc.hac(x, "avgsq")
+    monkeypatch.setenv("PC_GRAM_MIN_DIM", "4")
+    Z1 = pc.hac(x, "avgsq")
+    assert np.array_equal(Z0, Z1)

@@ -111,6 +111,53 @@ def complete_check(x, Z, rows, pair_limit=4e7):
     assert checked >= len(rows) // 2
 
 
+def avgsq_check(x, Z, rows, pair_limit=2e7):
+    """avg-2: sampled heights against the double-sum definition (oracle), and
+    the merged pair is a nearest pair among the clusters alive just before
+    it, with avg-2 values |cX - cC|^2 + Var(X)/|X| + Var(C)/|C| from FP64
+    node sums and spreads carried up the tree here."""
+    n = x.shape[0]
+    sums, sizes = oracle.tree_sums(x, Z)
+    a, b, birth, death = structure(Z, n, sizes)
+    cen = sums / sizes[:, None]
+    fs = sizes.astype(np.float64)
+    cab = ((cen[a] - cen[b]) ** 2).sum(1) * (fs[a] * fs[b] / (fs[a] + fs[b]))
+    var = [0.0] * (2 * n - 1)
+    al, bl, cl = a.tolist(), b.tolist(), cab.tolist()
+    for r in range(n - 1):
+        var[n + r] = var[al[r]] + var[bl[r]] + cl[r]
+    v = np.array(var) / fs
+    checked = 0
+    for r in rows:
+        A, B, h = a[r], b[r], Z[r, 2]
+        assert ((cen[A] - cen[B]) ** 2).sum() + v[A] + v[B] == pytest.approx(h, rel=1e-9), r
+        if fs[A] * fs[B] <= pair_limit:
+            MA, MB = oracle.node_members(Z, n, A), oracle.node_members(Z, n, B)
+            assert oracle.linkage_dist(x, "avgsq", MA, MB) == pytest.approx(h, rel=1e-9), r
+            checked += 1
+        alive = np.nonzero((birth < r) & (death >= r))[0]
+        alive = alive[(alive != A) & (alive != B)]
+        if alive.size == 0:
+            continue
+        for X in (A, B):
+            dv = ((cen[alive] - cen[X]) ** 2).sum(1) + v[alive] + v[X]
+            assert dv.min() >= h * (1 - 1e-9), (r, X)
+    assert checked >= len(rows) // 2
+
+
+def test_avgsq_1m_blobs(pc):
+    x = synth.blobs(1_000_000, 2, 50, 0.01, 11)
+    Z = pc.hac(x, "avgsq")
+    avgsq_check(x, Z, sample_rows(Z.shape[0], 40, 4))
+
+
+def test_avgsq_200k_d128(pc):
+    """The C4 point set under avg-2 (Gram search, centroid keys)."""
+    x = synth.WORKLOADS["vmf1000_200k_d128"]()
+    Z = pc.hac(x, "avgsq")
+    avgsq_check(x, Z, full_size_rows(Z, 9, k=12))
+
+
 def test_ward_1m_blobs(pc):
     x = synth.blobs(1_000_000, 2, 50, 0.01, 11)
     Z, st = pc.hac(x, "ward", return_stats=True)
