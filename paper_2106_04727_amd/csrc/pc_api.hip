@@ -2,6 +2,7 @@
 // of the round loop: validation, workspace layout, the per-round launches and
 // the few counter reads that size the next launches.
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -110,7 +111,14 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   S.gmin = c.take<unsigned long long>(gram ? d : 1);
   S.gmax = c.take<unsigned long long>(gram ? d : 1);
   S.gscale = c.take<double>(1);
-  S.term_pos = c.take<int>(gram ? n : 1);
+  // box tree: Ward / avg-2 at 3 <= d <= kTreeMaxDim (the call may still use another search)
+  const bool tree = centroid_link(linkage) && d >= 3 && d <= kTreeMaxDim;
+  S.term_pos = c.take<int>(gram || tree ? n : 1);
+  const size_t tnodes = n / 15 + 16;  // a 16-ary tree over n / 16 leaves (8 levels at most)
+  S.tree_lo = c.take<double>(tree ? tnodes * d : 1);
+  S.tree_hi = c.take<double>(tree ? tnodes * d : 1);
+  S.tree_nmin = c.take<int>(tree ? tnodes : 1);
+  S.tree_vmin = c.take<double>(tree ? tnodes : 1);
   S.t_best = c.take<double>(n);
   S.t_key = c.take<unsigned long long>(n);
   S.t_beta = c.take<double>(n);
@@ -391,11 +399,23 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   S.linkage = linkage;
   S.prune = prune;
   S.timing = (opt && opt->timing) ? 1 : 0;
-  // Ward and avg-2 keep the centroid grid through d = 5 (measured faster
-  // there than the Gram search on 1M-point 5-D sets); tuning knob PC_GRAM_MIN_DIM
-  int gram_min = centroid_link(linkage) ? 6 : kGramMinDim;
+  // Ward and avg-2 at 3 <= d <= 8 search a box tree over Morton-ordered
+  // centroids while many clusters are active and the Gram search once at most
+  // tree_gram_switch are (at d = 3, where there is no Gram search, the tree
+  // throughout). Without the tree: the centroid grid up to d = 5, the Gram
+  // search above. Tuning knobs: PC_TREE_MAX_DIM (0 = no tree),
+  // PC_TREE_GRAM_SWITCH (0 = tree in every round), PC_GRAM_MIN_DIM.
+  int tree_max = kTreeMaxDim;
+  if (const char *e = getenv("PC_TREE_MAX_DIM")) tree_max = std::min(kTreeMaxDim, atoi(e));
+  const bool tree_ok = prune && centroid_link(linkage) && d >= 3 && d <= tree_max;
+  int gram_min = centroid_link(linkage) && !tree_ok ? 6 : kGramMinDim;
   if (const char *e = getenv("PC_GRAM_MIN_DIM")) gram_min = std::max(kGramMinDim, atoi(e));
-  S.gram = (prune && d >= gram_min && d <= kGramMaxDim) ? 1 : 0;
+  const bool gram_ok = prune && d >= gram_min && d <= kGramMaxDim;
+  long long tree_gram_switch = 200000;  // measured on the paper's 1M-point 5-D sets (flat from 150K to 250K)
+  if (const char *e = getenv("PC_TREE_GRAM_SWITCH")) tree_gram_switch = atoll(e);
+  // the first round's search (tree_ok also fixes the Morton order of the init)
+  S.tree = tree_ok ? 1 : 0;
+  S.gram = (!tree_ok && gram_ok) ? 1 : 0;
   S.tev = ctx->tev;
   S.xin = nullptr;  // set once the device copy of the points is known
   double kms[4] = {0, 0, 0, 0};
@@ -423,7 +443,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     pc_status st = grow_part(ctx, S, 2LL * n + 64);
     if (st != PC_OK) return st;
   }
-  if (centroid_link(linkage) && S.gram) {
+  if (centroid_link(linkage) && gram_ok) {
     pc_status st = grow_cand(ctx, S, std::max<long long>(1 << 22, 4 * n));
     if (st != PC_OK) return st;
     if (const char *e = getenv("PC_TEST_CAND_CAP")) S.cand_cap = std::min<long long>(S.cand_cap, atoll(e));
@@ -489,6 +509,11 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   Counters &h = *ctx->hcnt;
   while (nact > 1) {
     if (rounds > n) return fail(PC_ERR_DEVICE, "round loop did not converge");
+    if (tree_ok) {
+      const bool use_tree = !gram_ok || tree_gram_switch <= 0 || nact > tree_gram_switch;
+      S.tree = use_tree ? 1 : 0;
+      S.gram = use_tree ? 0 : 1;
+    }
     bool need_pairs = false;
     S.tb0 = 0;
     S.tb1 = 0x7fffffff;
@@ -666,9 +691,13 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
       cache_cur = nxt;
     }
     take_times();
-    if (debug)
-      fprintf(stderr, "[parchain] round %lld done: nact %d nterm %d merged %d evals %lld pp %lld cand %lld\n", rounds,
-              nact, h.n_term, h.n_merge, h.cluster_evals, h.point_pairs, h.n_cand);
+    if (debug) {
+      const double now = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+      static thread_local double last = 0.0;
+      fprintf(stderr, "[parchain] round %lld done: nact %d nterm %d merged %d evals %lld pp %lld cand %lld (%.2f ms)\n",
+              rounds, nact, h.n_term, h.n_merge, h.cluster_evals, h.point_pairs, h.n_cand, last > 0.0 ? now - last : 0.0);
+      last = now;
+    }
     if (h.n_merge <= 0) return fail(PC_ERR_DEVICE, "round merged nothing");
     terms += h.n_term;
     ovfq += h.n_ovf;

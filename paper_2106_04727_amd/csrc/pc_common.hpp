@@ -21,6 +21,8 @@ constexpr int kExtMaxDim = 4;      // extreme-point bounds kept up to this d
 constexpr int kSupDirs = 64;       // d == 2, complete: support points in 64 fixed directions
 constexpr int kGramMinDim = 4;     // Gram (MFMA) search from this d on
 constexpr int kGramMaxDim = 128;   // largest d of the Gram search (K = 128 in LDS)
+constexpr int kTreeMaxDim = 8;     // Ward / avg-2: box-tree search over Morton-ordered centroids up to this d
+constexpr int kMortonAxes = 8;     // at most this many axes in the initial Morton order
 // MFMA depth of the Gram tiles: the dimension plus two augmented
 // coordinates (the norm terms of the bound pass), in steps of 16
 inline int gram_kp(int d) {
@@ -103,8 +105,8 @@ struct Counters {
   long long n_pairs;
   long long n_cand;
   long long n_pend;
-  unsigned long long bb_lo[2];
-  unsigned long long bb_hi[2];
+  unsigned long long bb_lo[kMortonAxes];  // ordered bits of the per-axis range
+  unsigned long long bb_hi[kMortonAxes];  // (points at init, active centroids per round)
   long long cluster_evals;
   long long point_pairs;
   long long n_tiles;
@@ -221,6 +223,16 @@ struct State {
   unsigned long long *gmin, *gmax;  // per-dimension ordered bits of the centroid range
   double *gscale;       // 1 value
   int *term_pos;        // active-list index of each terminal
+  // box tree (Ward / avg-2, 3 <= d <= kTreeMaxDim): an implicit 16-ary tree
+  // over the active list (leaves of 16 consecutive clusters); per node the FP64
+  // box of the centroids below it, the smallest size and smallest spread term.
+  // Level l holds tree_cnt[l] nodes from node tree_off[l]; level tree_top is the root.
+  int tree;
+  int tree_top;
+  int tree_cnt[8], tree_off[8];
+  double *tree_lo, *tree_hi;  // d per node
+  int *tree_nmin;
+  double *tree_vmin;
   int tb0, tb1;      // terminals [tb0, tb1) of the current Gram batch
   int cell_budget;  // grid cells a thread-per-terminal search visits before handing off
   double *tile_v;

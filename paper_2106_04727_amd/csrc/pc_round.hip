@@ -109,8 +109,10 @@ __global__ void k_reset_round(Counters *c) {
   c->n_pairs = 0;
   c->pair_overflow = 0;
   c->n_min = 0x7fffffff;
-  c->bb_lo[0] = c->bb_lo[1] = ~0ull;
-  c->bb_hi[0] = c->bb_hi[1] = 0ull;
+  for (int a = 0; a < kMortonAxes; ++a) {
+    c->bb_lo[a] = ~0ull;
+    c->bb_hi[a] = 0ull;
+  }
   c->n_tiles = 0;
 }
 
@@ -135,17 +137,26 @@ __global__ void k_check_finite(const float *x, long long count, Counters *c) {
 }
 
 __global__ void k_point_bbox(const float *x, int n, int d, int axes, Counters *c) {
-  unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
+  unsigned long long lo[kMortonAxes], hi[kMortonAxes];
+#pragma unroll
+  for (int a = 0; a < kMortonAxes; ++a) {
+    lo[a] = ~0ull;
+    hi[a] = 0ull;
+  }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    for (int a = 0; a < axes; ++a) {
-      unsigned long long b = ordered_bits((double)x[(size_t)i * d + a]);
-      lo[a] = b < lo[a] ? b : lo[a];
-      hi[a] = b > hi[a] ? b : hi[a];
-    }
-  for (int a = 0; a < 2; ++a) {
+#pragma unroll
+    for (int a = 0; a < kMortonAxes; ++a)
+      if (a < axes) {
+        unsigned long long b = ordered_bits((double)x[(size_t)i * d + a]);
+        lo[a] = b < lo[a] ? b : lo[a];
+        hi[a] = b > hi[a] ? b : hi[a];
+      }
+#pragma unroll
+  for (int a = 0; a < kMortonAxes; ++a) {
+    if (a >= axes) break;  // uniform: axes is a kernel argument
     unsigned long long l = block_reduce<unsigned long long, true>(lo[a]);
     unsigned long long h = block_reduce<unsigned long long, false>(hi[a]);
-    if (threadIdx.x == 0 && a < axes) {
+    if (threadIdx.x == 0) {
       atomicMin(&c->bb_lo[a], l);
       atomicMax(&c->bb_hi[a], h);
     }
@@ -161,20 +172,39 @@ __device__ __forceinline__ unsigned spread16(unsigned v) {
   return v;
 }
 
-// Morton (Z-order) code of the first one or two coordinates: spatially close
-// clusters get close slots, so one wavefront's terminals search nearby cells.
+// Morton (Z-order) code of the first `axes` coordinates: spatially close
+// clusters get close slots, so one wavefront's terminals search nearby cells
+// (grid) or lie in one small box (box tree). One or two axes: 16 bits each;
+// three to eight axes: 64 / axes bits each, interleaved into 64 bits.
+__device__ __forceinline__ int morton_bits(int axes) { return axes <= 2 ? 16 : 64 / axes; }
+
 __global__ void k_morton(const float *x, int n, int d, int axes, const Counters *c,
                          unsigned long long *key, unsigned *val) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  unsigned q[2] = {0, 0};
-  for (int a = 0; a < axes; ++a) {
-    double lo = from_ordered_bits(c->bb_lo[a]), hi = from_ordered_bits(c->bb_hi[a]);
-    double t = hi > lo ? ((double)x[(size_t)i * d + a] - lo) / (hi - lo) : 0.0;
-    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-    q[a] = (unsigned)(t * 65535.0);
+  const int bits = morton_bits(axes);
+  const double top = (double)((1u << bits) - 1u);
+  unsigned q[kMortonAxes];
+#pragma unroll
+  for (int a = 0; a < kMortonAxes; ++a) {
+    q[a] = 0;
+    if (a < axes) {
+      double lo = from_ordered_bits(c->bb_lo[a]), hi = from_ordered_bits(c->bb_hi[a]);
+      double t = hi > lo ? ((double)x[(size_t)i * d + a] - lo) / (hi - lo) : 0.0;
+      t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+      q[a] = (unsigned)(t * top);
+    }
   }
-  key[i] = axes == 2 ? (unsigned long long)(spread16(q[0]) | (spread16(q[1]) << 1)) : q[0];
+  if (axes <= 2) {
+    key[i] = axes == 2 ? (unsigned long long)(spread16(q[0]) | (spread16(q[1]) << 1)) : q[0];
+  } else {
+    unsigned long long k = 0;
+    for (int b = bits - 1; b >= 0; --b)
+#pragma unroll
+      for (int a = 0; a < kMortonAxes; ++a)
+        if (a < axes) k = (k << 1) | (unsigned long long)((q[a] >> b) & 1u);
+    key[i] = k;
+  }
   val[i] = (unsigned)i;
 }
 
@@ -1516,6 +1546,193 @@ __global__ __launch_bounds__(kBlock) void k_nn_full(State S, const int *list, co
   count_add(&S.cnt->point_pairs, ppairs);
   count_add(&S.cnt->visits[1], visits);
   count_add(&S.cnt->cache_hits, hits);
+}
+
+// ------------------------------------------------------ box-tree search ----
+// Ward and avg-2 at 3 <= d <= kTreeMaxDim. The active list is in slot order,
+// a Morton order over up to eight axes (clusters inherit the slot of their
+// lower-ID child, so the order stays spatially coherent as they merge). An
+// implicit 16-ary tree is built over it every round: leaves of kTreeFan
+// consecutive clusters, each level above grouping kTreeFan nodes, every node
+// with the FP64 box of its centroids, its smallest size and smallest spread
+// term (the range query of Alg. 3 over a bounding-box tree instead of a k-d
+// tree). One thread per terminal evaluates its own leaf first (a near
+// neighbour and a tight bound), then walks outward, bottom up, depth first
+// and without a stack (a node's parent is its index / 16), entering a node
+// only if its lower bound does not exceed the thread's bound (Sec. 4.1, 4.2:
+// the Ward and avg-2 keys grow with the centroid distance). Every loop step
+// does one box test or one candidate, so lanes of a wavefront stay in step.
+// A bound takes the key's FP64 operations in the same order on values no
+// larger than the key's operands, so it never exceeds a key (rounding is
+// monotone); pruning is strict, so equal keys reach the tie-break.
+constexpr int kTreeFan = 16;
+
+__global__ void k_tree_items(State S) {
+  const int nact = S.cnt->n_act, d = S.d;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nact; i += gridDim.x * blockDim.x) {
+    const int s = S.act[i];
+    S.item_meta[i] = make_int4(s, S.csize[s], S.cid[s], 0);
+    for (int k = 0; k < d; ++k) S.item_cen[(size_t)i * d + k] = S.wcen[(size_t)s * d + k];
+    if (S.linkage == kAvgSq) S.item_v[i] = S.cmv[s];
+  }
+}
+
+// one thread per node of level `lev`: the box of its (up to kTreeFan)
+// children, which are items for the leaves (lev 0)
+__global__ void k_tree_level(State S, int lev) {
+  const int d = S.d;
+  const int cnt = S.tree_cnt[lev];
+  const int nsrc = lev == 0 ? S.cnt->n_act : S.tree_cnt[lev - 1];
+  const int src0 = lev == 0 ? 0 : S.tree_off[lev - 1];
+  const int dst0 = S.tree_off[lev];
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += gridDim.x * blockDim.x) {
+    const int c0 = j * kTreeFan, c1 = min(c0 + kTreeFan, nsrc);
+    int nm = 0x7fffffff;
+    double vm = INFINITY;
+    for (int c = c0; c < c1; ++c) {
+      const int sz = lev == 0 ? S.item_meta[c].y : S.tree_nmin[src0 + c];
+      nm = sz < nm ? sz : nm;
+      if (S.linkage == kAvgSq) {
+        const double v = lev == 0 ? S.item_v[c] : S.tree_vmin[src0 + c];
+        vm = v < vm ? v : vm;
+      }
+    }
+    for (int k = 0; k < d; ++k) {
+      double lo = INFINITY, hi = -INFINITY;
+      for (int c = c0; c < c1; ++c) {
+        const double a = lev == 0 ? S.item_cen[(size_t)c * d + k] : S.tree_lo[(size_t)(src0 + c) * d + k];
+        const double b = lev == 0 ? a : S.tree_hi[(size_t)(src0 + c) * d + k];
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+      }
+      S.tree_lo[(size_t)(dst0 + j) * d + k] = lo;
+      S.tree_hi[(size_t)(dst0 + j) * d + k] = hi;
+    }
+    S.tree_nmin[dst0 + j] = nm;
+    S.tree_vmin[dst0 + j] = vm;
+  }
+}
+
+// lower bound of the key of the terminal (centroid ct, size nt, spread term
+// vt) and any cluster inside node `node`
+template <int LINK, int MAXD>
+__device__ __forceinline__ double tree_lb(const State &S, int node, const double *ct, double nt, double vt, int d) {
+  double q = 0.0;
+#pragma unroll
+  for (int k = 0; k < MAXD; ++k)
+    if (k < d) {
+      const double lo = S.tree_lo[(size_t)node * d + k], hi = S.tree_hi[(size_t)node * d + k];
+      const double g = lo > ct[k] ? lo - ct[k] : (ct[k] > hi ? ct[k] - hi : 0.0);
+      q += g * g;
+    }
+  if (LINK == kWard) {
+    const double nm = (double)S.tree_nmin[node];
+    return ((2.0 * nt * nm) / (nt + nm)) * q;
+  }
+  return q + (vt + S.tree_vmin[node]);
+}
+
+template <int LINK, int MAXD>
+__global__ __launch_bounds__(kBlock) void k_nn_tree(State S) {
+  const int nterm = S.cnt->n_term, nact = S.cnt->n_act, d = S.d;
+  const int ti = blockIdx.x * blockDim.x + threadIdx.x;
+  long long evals = 0, boxes = 0;
+  if (ti < nterm) {
+    const int t = S.term[ti];
+    double ct[MAXD];
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k) ct[k] = k < d ? S.wcen[(size_t)t * d + k] : 0.0;
+    const double nt = (double)S.csize[t];
+    const double vt = LINK == kAvgSq ? S.cmv[t] : 0.0;
+    const double bound = beta_key<LINK>(S.predd[t]);
+    double bestv = INFINITY;
+    unsigned long long bestk = kNoKey;
+    const int own = S.term_pos[ti] / kTreeFan;  // the terminal's own leaf
+    const int top = S.tree_top;
+    // Bottom up: the own leaf, then the subtrees of its siblings, then those
+    // of its parent's siblings, ... (nearest in Morton order first, so the
+    // bound tightens early). (al, anc): the ancestor whose subtree is done;
+    // sib: the sibling subtree being walked (-1: none yet at this level);
+    // (level, idx): the node to test next, item >= 0: walking leaf idx.
+    int al = 0, anc = own, sib = -1;
+    int level = 0, idx = own, item = 0;
+    bool done = false;
+    while (!done) {
+      if (item >= 0) {
+        const int i = idx * kTreeFan + item;
+        const int4 mt = S.item_meta[i];
+        double cv[MAXD];
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) cv[k] = k < d ? S.item_cen[(size_t)i * d + k] : 0.0;
+        const double v = cen_key<LINK, MAXD>(ct, nt, vt, cv, (double)mt.y, LINK == kAvgSq ? S.item_v[i] : 0.0, d);
+        ++evals;
+        const unsigned long long key = make_key(mt.z, mt.x);
+        if (mt.x != t && v <= bound && better(v, key, bestv, bestk)) {
+          bestv = v;
+          bestk = key;
+        }
+        if (++item < kTreeFan && i + 1 < nact) continue;
+        item = -1;
+      } else {
+        ++boxes;
+        const double lb = tree_lb<LINK, MAXD>(S, S.tree_off[level] + idx, ct, nt, vt, d);
+        if (!(lb > fmin(bound, bestv))) {
+          if (level > 0) {
+            --level;
+            idx *= kTreeFan;  // first child
+          } else {
+            item = 0;
+          }
+          continue;
+        }
+      }
+      // the node (level, idx) is finished: next node of the walk
+      for (;;) {
+        if (level == al) {
+          // a subtree at level al is finished: the next sibling of anc
+          const int p0 = (anc / kTreeFan) * kTreeFan, p1 = min(p0 + kTreeFan, S.tree_cnt[al]);
+          int nx = sib < 0 ? p0 : sib + 1;
+          if (nx == anc) ++nx;
+          if (nx < p1) {
+            sib = nx;
+            idx = nx;
+            break;
+          }
+          // every sibling done: the parent's subtree is done
+          if (al == top) {
+            done = true;
+            break;
+          }
+          anc /= kTreeFan;
+          ++al;
+          sib = -1;
+          level = al;
+          if (al == top) {  // the root has no siblings
+            done = true;
+            break;
+          }
+          continue;
+        }
+        if ((idx & (kTreeFan - 1)) != kTreeFan - 1 && idx + 1 < S.tree_cnt[level]) {
+          ++idx;
+          break;
+        }
+        idx /= kTreeFan;
+        ++level;
+      }
+    }
+    if (bestk == kNoKey) {
+      // the predecessor bound held nothing (cannot happen for an exact bound):
+      // the full scan takes the terminal without a bound
+      const int o = atomicAdd(&S.cnt->n_ovf, 1);
+      S.ovf[o] = ti;
+    } else {
+      S.t_best[ti] = bestv;
+      S.t_key[ti] = bestk;
+    }
+  }
+  count_add(&S.cnt->cluster_evals, evals);
+  count_add(&S.cnt->visits[0], evals + boxes);
 }
 
 // ---------------------------------------------------------- pair tiles ----
@@ -3194,6 +3411,32 @@ void launch_search(State &S, int nact, hipStream_t s, int *t_ovf) {
   }
 }
 
+// box tree: items in active-list order, the node boxes level by level, the
+// search, then the full scan for any terminal it handed back
+template <int LINK>
+void launch_tree_search(State &S, int nact, hipStream_t s) {
+  int cnt = (nact + kTreeFan - 1) / kTreeFan, off = 0, lev = 0;
+  for (;;) {
+    S.tree_cnt[lev] = cnt;
+    S.tree_off[lev] = off;
+    off += cnt;
+    if (cnt == 1) break;
+    cnt = (cnt + kTreeFan - 1) / kTreeFan;
+    ++lev;
+  }
+  S.tree_top = lev;
+  k_tree_items<<<nblk(nact, 1 << 20), kBlock, 0, s>>>(S);
+  for (int l = 0; l <= S.tree_top; ++l) k_tree_level<<<nblk(S.tree_cnt[l], 1 << 20), kBlock, 0, s>>>(S, l);
+  tmark(S, 0, false, s);
+  if (S.d <= 4) k_nn_tree<LINK, 4><<<nblk(nact, 1 << 20), kBlock, 0, s>>>(S);
+  else k_nn_tree<LINK, 8><<<nblk(nact, 1 << 20), kBlock, 0, s>>>(S);
+  tmark(S, 0, true, s);
+  tmark(S, 1, false, s);
+  const size_t sm = (size_t)S.d * (sizeof(double) + 2 * sizeof(float));
+  k_nn_full<LINK><<<256, kBlock, sm, s>>>(S, S.ovf, &S.cnt->n_ovf);
+  tmark(S, 1, true, s);
+}
+
 template <int LINK>
 void launch_emit(State &S, int nact, hipStream_t s, int *t_ovf) {
   // pass 1 of the ring search; the full-scan kernel already emitted its pairs
@@ -3332,11 +3575,13 @@ void launch_check_finite(const float *x, long long count, Counters *cnt, hipStre
 
 void launch_init(State &S, const float *x, hipStream_t s) {
   const int n = S.n;
-  const int axes = S.d >= 2 ? 2 : 1;
+  // the box tree orders points over all (up to 8) axes, the grid over two
+  const int axes = S.tree ? std::min(S.d, kMortonAxes) : (S.d >= 2 ? 2 : 1);
+  const int key_bits = axes <= 2 ? 16 * axes : axes * (64 / axes);
   k_reset_round<<<1, 1, 0, s>>>(S.cnt);
   k_point_bbox<<<nblk(n, 1024), kBlock, 0, s>>>(x, n, S.d, axes, S.cnt);
   k_morton<<<nblk(n, 1 << 22), kBlock, 0, s>>>(x, n, S.d, axes, S.cnt, S.sk0, S.sv0);
-  radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, n, axes == 2 ? 32 : 16, S.hist, S.part, s);
+  radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, n, key_bits, S.hist, S.part, s);
   k_init_slots<<<nblk(n, 1 << 22), kBlock, 0, s>>>(S, x, S.sv0);
   k_set_nact<<<1, 1, 0, s>>>(S.cnt, n);
   if (S.p16) {
@@ -3355,7 +3600,7 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
   k_act_pass<<<gb, kBlock, 0, s>>>(S, round);
   scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, &S.cnt->n_term, S.part, s);
   k_scatter_flagged<<<gb, kBlock, 0, s>>>(S.act, S.flags, S.scan, &S.cnt->n_act, S.term);
-  if (S.d <= kGridMaxDim && S.prune && !S.gram) {
+  if (S.d <= kGridMaxDim && S.prune && !S.gram && !S.tree) {
     k_grid_params<<<1, 1, 0, s>>>(S, S.cell_cap);
     k_zero_cells<<<nblk(nact + 1, 2048), kBlock, 0, s>>>(S);
     k_cell_count<<<gb, kBlock, 0, s>>>(S);
@@ -3371,6 +3616,12 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
     k_term_pos<<<gb, kBlock, 0, s>>>(S);
     launch_gram_setup(S, nact, s);
     need_pairs = !centroid_link(S.linkage);
+    return;
+  }
+  if (S.tree) {
+    k_term_pos<<<gb, kBlock, 0, s>>>(S);
+    if (S.linkage == kWard) launch_tree_search<kWard>(S, nact, s);
+    else launch_tree_search<kAvgSq>(S, nact, s);
     return;
   }
   switch (S.linkage) {

@@ -70,6 +70,7 @@ def test_fig1_worked_example(pc):
     (2000, 3, "u", 6), (3000, 10, "b", 7), (700, 16, "u", 8), (500, 40, "b", 9),
     (1500, 4, "u", 10), (2000, 64, "b", 11), (2500, 128, "s", 12), (800, 100, "s", 13),
     (400, 200, "b", 14),  # beyond the Gram search: full scan and generic tiles
+    (3000, 6, "b", 15), (2500, 8, "u", 16),  # Ward / avg-2: box tree up to d = 8
 ])
 def test_parity_small(pc, link, n, d, kind, seed):
     if kind == "u":
@@ -283,9 +284,11 @@ def test_avgsq_hand_computed_instances(pc):
 
 @pytest.mark.parametrize("d", [2, 3, 5])
 def test_avgsq_ring_handoff(pc, d, monkeypatch):
-    """avg-2 on the centroid grid: a one-cell budget hands every terminal to
-    the block ring search; rows must not change."""
+    """avg-2 on the centroid grid (the box tree switched off at d = 3, 5): a
+    one-cell budget hands every terminal to the block ring search; rows must
+    not change."""
     x = synth.blobs(8000, d, 40, 0.01, 70 + d)
+    monkeypatch.setenv("PC_TREE_MAX_DIM", "0")
     Z0 = pc.hac(x, "avgsq")
     monkeypatch.setenv("PC_CELL_BUDGET", "1")
     Z1, st = pc.hac(x, "avgsq", return_stats=True)
@@ -302,3 +305,31 @@ def test_avgsq_gram_from_dim_four(pc, monkeypatch):
     monkeypatch.setenv("PC_GRAM_MIN_DIM", "4")
     Z1 = pc.hac(x, "avgsq")
     assert np.array_equal(Z0, Z1)
+
+
+@pytest.mark.parametrize("link", ["ward", "avgsq"])
+@pytest.mark.parametrize("d,kind", [(3, "u"), (4, "b"), (5, "u"), (5, "b"), (8, "b")])
+def test_box_tree_equals_other_searches(pc, link, d, kind, monkeypatch):
+    """Ward / avg-2 at 3 <= d <= 8 search a box tree over Morton-ordered
+    centroids in the rounds with many active clusters, the Gram search in the
+    others; the grid (d <= 5), the Gram search and the full scan evaluate the
+    same FP64 keys, so every mix must give identical rows, matching the
+    oracle."""
+    n = 6000
+    x = synth.uniform(n, d, 80 + d) if kind == "u" else synth.blobs(n, d, 30, 0.02, 80 + d)
+    monkeypatch.setenv("PC_TREE_GRAM_SWITCH", "0")  # the tree in every round
+    Zt, st = pc.hac(x, link, return_stats=True)
+    assert st["kernels"]["ring_search"]["visits"] > 0
+    monkeypatch.setenv("PC_TREE_GRAM_SWITCH", "1500")  # tree, then Gram (d >= 4)
+    assert np.array_equal(Zt, pc.hac(x, link))
+    monkeypatch.delenv("PC_TREE_GRAM_SWITCH")
+    assert np.array_equal(Zt, pc.hac(x, link))
+    monkeypatch.setenv("PC_TREE_MAX_DIM", "0")
+    Zo = pc.hac(x, link)  # grid up to d = 5, Gram search above
+    assert np.array_equal(Zt, Zo)
+    monkeypatch.setenv("PC_GRAM_MIN_DIM", "4")
+    assert np.array_equal(Zt, pc.hac(x, link))
+    assert np.array_equal(Zt, pc.hac(x, link, prune=False))
+    Zr, cert = oracle.nnchain(x, link, threads=8)
+    if cert["min_gap"] >= 1e-10:
+        assert _trees.same_tree(Zt, Zr, n, rtol=RTOL[link])

@@ -158,6 +158,18 @@ def test_avgsq_200k_d128(pc):
     avgsq_check(x, Z, full_size_rows(Z, 9, k=12))
 
 
+@pytest.mark.parametrize("link", ["ward", "avgsq"])
+def test_box_tree_5d_1m(pc, link):
+    """The paper's 5-D GaussianDisc law at 1M points (box-tree search)."""
+    x = synth.WORKLOADS["5G1M"]()
+    Z = pc.hac(x, link)
+    rows = sample_rows(Z.shape[0], 20, 5)
+    if link == "ward":
+        ward_check(x, Z, rows)
+    else:
+        avgsq_check(x, Z, rows)
+
+
 def test_ward_1m_blobs(pc):
     x = synth.blobs(1_000_000, 2, 50, 0.01, 11)
     Z, st = pc.hac(x, "ward", return_stats=True)
