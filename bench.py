@@ -170,6 +170,46 @@ def paper_leg(pc, synth, torch, ctx, stream):
     return out
 
 
+def ablation_leg(pc, synth, torch, ctx, stream):
+    """The paper's two ablations, on its GaussianDisc law in 2-D (Sec. 6):
+    the range-query pruning of Alg. 3 on and off (its "no range query"
+    comparison), at sizes where the unpruned search still finishes; and
+    the cluster-pair cache size s in {0, 16, 64, 256} slots per cluster
+    (Sec. 5; the paper uses s = 64) for average and complete linkage on 2G1M."""
+    dev = torch.device("cuda:0")
+
+    def run(x, link, **kw):
+        xt = torch.from_numpy(x).to(dev)
+        pc.hac_device(xt[:4000].contiguous(), link, ctx=ctx, stream=stream, **kw)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = pc.hac_device(xt, link, ctx=ctx, stream=stream, **kw)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, st
+
+    out = {"pruning": {}, "cache": {}}
+    for link in ("ward", "avgsq", "complete", "average"):
+        # the unpruned search evaluates every pair: O(n^2) centroid pairs per
+        # round for Ward / avg-2, O(n^2) point pairs for complete / average
+        x = synth.gaussian_disc(100_000 if link in ("ward", "avgsq") else 20_000, 2, 71)
+        row = {"n": int(x.shape[0])}
+        for prune in (True, False):
+            sec, st = run(x, link, prune=prune)
+            row["on" if prune else "off"] = {"s": sec, "cluster_evals": st["cluster_evals"],
+                                             "point_pair_evals": st["point_pair_evals"]}
+        row["speedup"] = row["off"]["s"] / row["on"]["s"]
+        out["pruning"][link] = row
+    x = synth.WORKLOADS["2G1M"]()
+    for link in ("average", "complete"):
+        row = {}
+        for slots in (0, 16, 64, 256):
+            sec, st = run(x, link, cache_slots=slots)
+            row[str(slots)] = {"s": sec, "hits": st["cache_hits"], "inserts": st["cache_inserts"],
+                               "derived": st["cache_derived"], "point_pair_evals": st["point_pair_evals"]}
+        out["cache"][link] = row
+    return out
+
+
 def serve_bench(num, slots, n_max):
     """Serving leg: a Poisson trace of clustering requests of uneven n, d and
     linkage (the serving law of ``synth.serving_trace``), first solved one at
@@ -261,6 +301,8 @@ def main():
     ap.add_argument("--serve-nmax", type=int, default=200_000)
     ap.add_argument("--workload", default="blob50_1m_d2",
                     help="named input of synth.WORKLOADS (the headline is blob50_1m_d2)")
+    ap.add_argument("--ablations", action="store_true",
+                    help="also run the pruning on/off and cache-size ablations")
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy 256 MiB on the device first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -394,6 +436,12 @@ def main():
 
     if not args.no_extra and args.workload == "blob50_1m_d2":
         out["paper_sets"] = paper_leg(pc, synth, torch, ctx, stream)
+
+    if args.ablations:
+        try:
+            out["ablations"] = ablation_leg(pc, synth, torch, ctx, stream)
+        except Exception as e:  # reported, never hidden
+            out["ablations"] = {"error": str(e)}
 
     if args.serve_requests > 0:
         try:

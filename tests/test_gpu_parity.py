@@ -317,12 +317,14 @@ def test_box_tree_equals_other_searches(pc, link, d, kind, monkeypatch):
     oracle."""
     n = 6000
     x = synth.uniform(n, d, 80 + d) if kind == "u" else synth.blobs(n, d, 30, 0.02, 80 + d)
+    monkeypatch.setenv("PC_TREE_MAX_DIM", "8")  # the default stops at d = 5
     monkeypatch.setenv("PC_TREE_GRAM_SWITCH", "0")  # the tree in every round
     Zt, st = pc.hac(x, link, return_stats=True)
     assert st["kernels"]["ring_search"]["visits"] > 0
     monkeypatch.setenv("PC_TREE_GRAM_SWITCH", "1500")  # tree, then Gram (d >= 4)
     assert np.array_equal(Zt, pc.hac(x, link))
     monkeypatch.delenv("PC_TREE_GRAM_SWITCH")
+    monkeypatch.delenv("PC_TREE_MAX_DIM")
     assert np.array_equal(Zt, pc.hac(x, link))
     monkeypatch.setenv("PC_TREE_MAX_DIM", "0")
     Zo = pc.hac(x, link)  # grid up to d = 5, Gram search above
