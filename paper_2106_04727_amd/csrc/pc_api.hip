@@ -105,6 +105,9 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   S.gq = c.take<float4>(gram ? n : 1);
   S.p16 = gram && pts ? c.take<_Float16>(n * kp) : nullptr;
   S.pq = c.take<float4>(gram && pts ? n : 1);
+  const bool blk = gram && comp && d <= kBlkMaxDim;
+  S.blk_lo = c.take<float>(blk ? (n / 64 + 2) * d : 1);
+  S.blk_hi = c.take<float>(blk ? (n / 64 + 2) * d : 1);
   S.porg = c.take<double>(gram ? d : 1);
   S.pscale = c.take<double>(1);
   S.gorg = c.take<double>(gram ? d : 1);
@@ -259,7 +262,7 @@ size_t pc_hac_workspace_bytes(int64_t n, int32_t d, int32_t linkage, const pc_op
   const bool gram = d >= kGramMinDim && d <= kGramMaxDim;
   // initial candidate record (grown on demand), pair list, tiles and filter
   const size_t cand = (size_t)std::max<int64_t>(1 << 22, 4 * n);
-  const size_t per_cand = 2 * sizeof(double) + sizeof(long long) + sizeof(int4) + 4 * sizeof(int);
+  const size_t per_cand = 3 * sizeof(double) + sizeof(long long) + sizeof(int4) + 4 * sizeof(int);
   if (!centroid_link(linkage) || gram) bytes += cand * per_cand + 1024;
   bytes += ((size_t)(2 * n + 64) / 1024 + 1024) * sizeof(long long);
   if (!centroid_link(linkage)) {
@@ -330,15 +333,16 @@ static pc_status grow_tiles(pc_context *ctx, State &S, long long cap) {
 
 static pc_status grow_cand(pc_context *ctx, State &S, long long cap) {
   if (cap > kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round needs more than 2^30 recorded candidates");
-  // per candidate: lower bound, value (f64), tile prefix (i64), point ranges
-  // (int4), terminal, cluster, small-list entry (i32)
-  const size_t per = 2 * sizeof(double) + sizeof(long long) + sizeof(int4) + 4 * sizeof(int);
+  // per candidate: lower bound, value, screening bound (f64), tile prefix
+  // (i64), point ranges (int4), terminal, cluster, small-list entry (i32)
+  const size_t per = 3 * sizeof(double) + sizeof(long long) + sizeof(int4) + 4 * sizeof(int);
   HIPCHK(grow(ctx->cand, (size_t)cap * per + 1024));
   const long long cc = (long long)((ctx->cand.bytes - 1024) / per);
   S.cand_cap = cc;
   S.cd_lb = (double *)ctx->cand.p;
   S.cd_v = S.cd_lb + cc;
-  S.cd_tile0 = (long long *)(S.cd_v + cc);
+  S.cd_l0 = S.cd_v + cc;
+  S.cd_tile0 = (long long *)(S.cd_l0 + cc);  // 32 cc bytes in: the int4 records stay 16-byte aligned
   S.cd_desc = (int4 *)(S.cd_tile0 + cc);
   S.cd_t = (int *)(S.cd_desc + cc);
   S.cd_c = S.cd_t + cc;

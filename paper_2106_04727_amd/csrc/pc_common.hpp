@@ -17,7 +17,8 @@ constexpr int kGridMaxDim = 16;    // ring search over a centroid grid up to thi
 constexpr int kInlinePairs = 64;   // |t|*|C| at or below this: evaluated inside the search
 constexpr int kTile = 64;          // point-pair tile edge for deferred evaluations
 constexpr int kChunk = 256;        // points per filter block (complete linkage)
-constexpr int kExtMaxDim = 4;      // extreme-point bounds kept up to this d
+constexpr int kExtMaxDim = 8;      // extreme-point bounds kept up to this d
+constexpr int kBlkMaxDim = 16;     // complete: 64-point block boxes prune interval tiles up to this d
 constexpr int kSupDirs = 64;       // d == 2, complete: support points in 64 fixed directions
 constexpr int kGramMinDim = 4;     // Gram (MFMA) search from this d on
 constexpr int kGramMaxDim = 128;   // largest d of the Gram search (K = 128 in LDS)
@@ -218,6 +219,8 @@ struct State {
   int *cd_small;  // small candidates (exact now)
   int4 *cd_desc;  // screened candidates (dense): row begin, rows, column begin, columns
   int *cd_scr;    // screened candidates (dense): candidate index
+  double *cd_l0;  // screened candidates (dense), complete: a lower bound of the key fixed before the tiles
+  float *blk_lo, *blk_hi;  // complete, d <= kBlkMaxDim: box of each 64-position block of points (d each)
   int *nparent;  // node -> parent node (-1: none yet); kept when the cache is on
   double *gorg;         // d
   unsigned long long *gmin, *gmax;  // per-dimension ordered bits of the centroid range

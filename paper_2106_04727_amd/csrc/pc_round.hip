@@ -1876,13 +1876,16 @@ __global__ void k_pair_prep_comp(State S, long long *nch) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
     int r, q;
     pair_slots(S, p, r, q);
-    if (!(S.pr_v[p] >= 0.0)) {
+    const double v0 = S.pr_v[p];
+    if (!(v0 >= 0.0) || S.gram) {
+      // the largest of: the bound the pair came with (Gram search: its
+      // screened L), the box / spread bounds, the extreme-point pairs
       const double *cr = S.wcen + (size_t)r * d, *cq = S.wcen + (size_t)q * d;
       double lb, ub;
       pair_bounds<kComplete, 0>(cr, S.lo + (size_t)r * d, S.hi + (size_t)r * d, cq, S.lo + (size_t)q * d,
                                 S.hi + (size_t)q * d, d, lb, ub, spread_lo(S, r) + spread_lo(S, q));
       comp_lb_refine(S, r, q, d, lb);
-      S.pr_v[p] = lb;
+      S.pr_v[p] = v0 > lb ? v0 : lb;
     }
     S.pr_kR[p] = 0;
     S.pr_kS[p] = 0;
@@ -2757,6 +2760,44 @@ __global__ void k_pt_prep(State S) {
 // pairs get their tile count and point ranges for the interval pass (the
 // cache is consulted only for the pairs that survive it). cd_lb < 0 marks a
 // candidate whose exact value is in cd_v.
+// complete, d <= kBlkMaxDim: the box of every 64-position block of the points
+// in their current places (FP32, exact), once per round
+__global__ void k_blk_boxes(State S) {
+  const int n = S.n, d = S.d;
+  const int nb = (n + 63) / 64;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+    const int p0 = b * 64, p1 = min(p0 + 64, n);
+    for (int k = 0; k < d; ++k) {
+      float lo = INFINITY, hi = -INFINITY;
+      for (int p = p0; p < p1; ++p) {
+        const float v = S.px[(size_t)p * d + k];
+        lo = fminf(lo, v);
+        hi = fmaxf(hi, v);
+      }
+      S.blk_lo[(size_t)b * d + k] = lo;
+      S.blk_hi[(size_t)b * d + k] = hi;
+    }
+  }
+}
+
+// Upper bound of the squared distance of any point at positions [a, a + na)
+// and any at [b, b + nb): per coordinate the farthest ends of the two unions
+// of block boxes (at most two blocks per side), summed in FP64 and rounded up.
+__device__ __forceinline__ double blk_far_ub(const State &S, int a, int na, int b, int nb) {
+  const int d = S.d;
+  const int a0 = a / 64, a1 = (a + na - 1) / 64, b0 = b / 64, b1 = (b + nb - 1) / 64;
+  double q = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double la = fmin((double)S.blk_lo[(size_t)a0 * d + k], (double)S.blk_lo[(size_t)a1 * d + k]);
+    const double ha = fmax((double)S.blk_hi[(size_t)a0 * d + k], (double)S.blk_hi[(size_t)a1 * d + k]);
+    const double lb = fmin((double)S.blk_lo[(size_t)b0 * d + k], (double)S.blk_lo[(size_t)b1 * d + k]);
+    const double hb = fmax((double)S.blk_hi[(size_t)b0 * d + k], (double)S.blk_hi[(size_t)b1 * d + k]);
+    const double e = fmax(ha - lb, hb - la);
+    q += e * e;
+  }
+  return q * (1.0 + 1e-12);
+}
+
 template <int LINK>
 __global__ void k_cand_triage(State S, int ncand) {
   const int d = S.d;
@@ -2774,7 +2815,21 @@ __global__ void k_cand_triage(State S, int ncand) {
       S.cd_tile0[k] = (long long)((nt + kGT - 1) / kGT) * ((nc + kGT - 1) / kGT);
       S.cd_desc[k] = make_int4(S.cbeg[t], nt, S.cbeg[c], nc);
       S.cd_scr[k] = i;
-      S.cd_lb[i] = 0.0;
+      double l0 = 0.0;
+      if (LINK == kComplete) {
+        // a lower bound of the key before any tile: the spread and box bounds
+        // and, up to d = kExtMaxDim, the largest distance among the two
+        // clusters' extreme points (a real pair); tiles whose block boxes
+        // stay below it cannot hold the farthest pair
+        double lb, ub;
+        pair_bounds<kComplete, 0>(S.wcen + (size_t)t * d, S.lo + (size_t)t * d, S.hi + (size_t)t * d,
+                                  S.wcen + (size_t)c * d, S.lo + (size_t)c * d, S.hi + (size_t)c * d, d, lb, ub,
+                                  spread_lo(S, t) + spread_lo(S, c));
+        comp_lb_refine(S, t, c, d, lb);
+        l0 = lb > 0.0 ? lb * (1.0 - 1e-9) : 0.0;
+      }
+      S.cd_l0[k] = l0;
+      S.cd_lb[i] = l0;
       S.cd_v[i] = 0.0;
     }
   }
@@ -2882,7 +2937,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
   uint4 reg[NCH];
   float4 rq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   int cur_i = 0, cur_nr = 0, cur_nc = 0;
-  auto fetch = [&](long long tile) {
+  // complete, d <= kBlkMaxDim: a tile whose block boxes cannot reach the
+  // candidate's fixed lower bound holds no farthest pair and is skipped (the
+  // tile holding the farthest pair always reaches it, so L and H stay valid);
+  // the decision uses values no thread writes during the kernel, so it is
+  // uniform over the block
+  const bool prune = LINK == kComplete && KP <= 32 && S.d <= kBlkMaxDim;  // compiled out above K = 32
+  int ba = 0, bb = 0, nr = 0, nc = 0;
+  auto locate = [&](long long tile) {
     if (tile >= oend) {
       ++own;
       ostart = oend;
@@ -2894,8 +2956,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
     const long long local = tile - ostart;
     const int ntc = (ds.w + kGT - 1) / kGT;
     const int r0 = (int)(local / ntc) * kGT, c0 = (int)(local % ntc) * kGT;
-    const int nr = min(kGT, ds.y - r0), nc = min(kGT, ds.w - c0);
-    const int ba = ds.x + r0, bb = ds.z + c0;
+    // uniform over the block by construction: kept in scalar registers
+    nr = __builtin_amdgcn_readfirstlane(min(kGT, ds.y - r0));
+    nc = __builtin_amdgcn_readfirstlane(min(kGT, ds.w - c0));
+    ba = __builtin_amdgcn_readfirstlane(ds.x + r0);
+    bb = __builtin_amdgcn_readfirstlane(ds.z + c0);
+  };
+  auto fetch = [&](long long tile) {
+    locate(tile);
 #pragma unroll
     for (int u = 0; u < NCH; ++u) {
       const int j = threadIdx.x + u * kBlock;
@@ -2912,8 +2980,54 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
     cur_nr = nr;
     cur_nc = nc;
   };
-  fetch(ta);
-  for (long long tile = ta; tile < te; ++tile) {
+  // the first tile at or after `tile` that is not skipped (its points
+  // loaded), or te. The bound is the entry's fixed L0, raised for the entry
+  // of the last snapshot to the running lower bound that thread 0 read into
+  // LDS before the last barrier (the same value for every thread).
+  // (tiles are visited one by one in order, so locate() crosses at most one
+  // entry per tile, and locating a tile twice changes nothing)
+  // With pruning, the block tests a window of up to kBlock tiles of one
+  // entry at once (a thread per tile) and takes the first one kept.
+  __shared__ double snap_lb;
+  __shared__ int snap_own;
+  __shared__ long long win_first[kBlock / kWave];
+  if (threadIdx.x == 0) snap_own = -1;
+  __syncthreads();
+  auto next_tile = [&](long long tile) -> long long {
+    if (!prune) {
+      if (tile < te) fetch(tile);
+      return tile < te ? tile : te;
+    }
+    while (tile < te) {
+      locate(tile);  // enters the tile's entry (at most one crossing)
+      const long long wend = min(min(oend, te), tile + (long long)kBlock);
+      double thr = S.cd_l0[own];
+      if (own == snap_own) thr = fmax(thr, snap_lb);
+      const long long my = tile + threadIdx.x;
+      long long cand = LLONG_MAX;
+      if (my < wend) {
+        const long long local = my - ostart;
+        const int ntc = (ds.w + kGT - 1) / kGT;
+        const int r0 = (int)(local / ntc) * kGT, c0 = (int)(local % ntc) * kGT;
+        const int mr = min(kGT, ds.y - r0), mc = min(kGT, ds.w - c0);
+        if (!(blk_far_ub(S, ds.x + r0, mr, ds.z + c0, mc) < thr)) cand = my;
+      }
+      cand = wave_min(cand);
+      __syncthreads();  // the previous window's reads of win_first are done
+      if ((threadIdx.x & (kWave - 1)) == 0) win_first[threadIdx.x / kWave] = cand;
+      __syncthreads();
+      long long first = win_first[0];
+      for (int q = 1; q < kBlock / kWave; ++q) first = win_first[q] < first ? win_first[q] : first;
+      if (first < wend) {
+        fetch(first);  // inside the entry located above: no crossing
+        return first;
+      }
+      tile = wend;
+    }
+    return te;
+  };
+  long long tile = next_tile(ta);
+  while (tile < te) {
     const int i = cur_i, nr = cur_nr, ncl = cur_nc;
     __syncthreads();
 #pragma unroll
@@ -2923,6 +3037,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
         const int sd = j / (kGT * CH), r = (j / CH) % kGT, c8 = j % CH;
         *(uint4 *)&sab[sd][r][c8 * 8] = reg[u];
       }
+    }
+    if (prune && threadIdx.x == 0) {
+      // the running lower bound of the current entry (tiles raise it)
+      snap_lb = __hip_atomic_load(&S.cd_lb[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      snap_own = own;
     }
     if (w < 2) {
       an[w][lane] = rq.x;
@@ -2939,7 +3058,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
       }
     }
     __syncthreads();
-    if (tile + 1 < te) fetch(tile + 1);  // in flight during the tile's arithmetic
+    const long long nxt = next_tile(tile + 1);  // its points in flight during the tile's arithmetic
     float16v acc = {};
 #pragma unroll
     for (int kk = 0; kk < KP; kk += 16) {
@@ -3025,6 +3144,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
         atomicMax((unsigned long long *)&S.cd_v[i], pos_bits(th * th * isc * isc));
       }
     }
+    tile = nxt;
   }
   count_add(&S.cnt->visits[1], pairs);  // nonzero in thread 0 only
 }
@@ -3102,7 +3222,9 @@ __global__ void k_gram_exact(State S) {
           if (p < S.pair_cap) {
             S.pr_t[p] = ti;
             S.pr_c[p] = c;
-            S.pr_v[p] = -1.0;
+            // complete: the candidate's lower bound (the screened L, or 0)
+            // starts the exact pass; the pair prep raises it further
+            S.pr_v[p] = LINK == kComplete && lb >= 0.0 ? lb : -1.0;
           } else {
             S.cnt->pair_overflow = 1;
           }
@@ -3506,6 +3628,8 @@ void launch_gram_setup(State &S, int nact, hipStream_t s) {
   k_gram_setup<<<1, kGramMaxDim, 0, s>>>(S);
   k_gram_prep<<<nblk((long long)nact * kWave, 4096), kBlock, 0, s>>>(S);
   if (S.p16) k_pt_prep<<<nblk((long long)S.n * kWave, 4096), kBlock, 0, s>>>(S);
+  if (S.p16 && S.linkage == kComplete && S.d <= kBlkMaxDim)
+    k_blk_boxes<<<nblk((S.n + 63) / 64, 4096), kBlock, 0, s>>>(S);
 }
 
 template <int LINK>
