@@ -28,7 +28,7 @@ def requests(seed=5):
     for i in range(14):
         n = int(np.exp(rng.uniform(np.log(256), np.log(6000))))
         d = int(rng.choice([2, 3, 10, 64]))
-        link = ["complete", "average", "ward"][i % 3]
+        link = ["complete", "average", "ward", "avgsq"][i % 4]
         k = int(rng.integers(5, 101))
         sigma = float(rng.uniform(0.01, 0.05))
         out.append((synth.blobs(n, d, k, sigma, 100 + i), link))
@@ -49,7 +49,7 @@ def test_alone_equals_in_the_mix(pc):
     # and two of them against the oracle
     for (x, link), m in list(zip(reqs, mixed))[:2]:
         Zo, _ = oracle.nnchain(x, link, threads=8)
-        assert _trees.same_tree(m, Zo, x.shape[0], rtol=1e-12 if link == "average" else 0.0)
+        assert _trees.same_tree(m, Zo, x.shape[0], rtol={"average": 1e-12, "avgsq": 1e-10}.get(link, 0.0))
 
 
 def test_failed_request_does_not_stop_the_server(pc):
