@@ -1876,16 +1876,17 @@ __global__ void k_pair_prep_comp(State S, long long *nch) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
     int r, q;
     pair_slots(S, p, r, q);
-    const double v0 = S.pr_v[p];
-    if (!(v0 >= 0.0) || S.gram) {
-      // the largest of: the bound the pair came with (Gram search: its
-      // screened L), the box / spread bounds, the extreme-point pairs
+    if (!(S.pr_v[p] >= 0.0)) {
+      // no bound yet (a screened pair brings its L): box / spread bounds and
+      // the extreme-point pairs
       const double *cr = S.wcen + (size_t)r * d, *cq = S.wcen + (size_t)q * d;
       double lb, ub;
       pair_bounds<kComplete, 0>(cr, S.lo + (size_t)r * d, S.hi + (size_t)r * d, cq, S.lo + (size_t)q * d,
                                 S.hi + (size_t)q * d, d, lb, ub, spread_lo(S, r) + spread_lo(S, q));
-      comp_lb_refine(S, r, q, d, lb);
-      S.pr_v[p] = v0 > lb ? v0 : lb;
+      // the (2d)^2 extreme-point pairs pay off for large pairs (above 4-D
+      // their count grows faster than the filter saves on small ones)
+      if (d <= 4 || (long long)S.csize[r] * S.csize[q] >= 4096) comp_lb_refine(S, r, q, d, lb);
+      S.pr_v[p] = lb;
     }
     S.pr_kR[p] = 0;
     S.pr_kS[p] = 0;
@@ -3222,9 +3223,10 @@ __global__ void k_gram_exact(State S) {
           if (p < S.pair_cap) {
             S.pr_t[p] = ti;
             S.pr_c[p] = c;
-            // complete: the candidate's lower bound (the screened L, or 0)
-            // starts the exact pass; the pair prep raises it further
-            S.pr_v[p] = LINK == kComplete && lb >= 0.0 ? lb : -1.0;
+            // complete: a screened candidate's lower bound L (within the
+            // FP16 error of the value) starts the exact pass; others get
+            // theirs from the pair prep
+            S.pr_v[p] = LINK == kComplete && lb > 0.0 ? lb : -1.0;
           } else {
             S.cnt->pair_overflow = 1;
           }
