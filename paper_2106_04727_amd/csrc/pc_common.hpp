@@ -238,6 +238,7 @@ struct State {
   double *tree_vmin;
   int tb0, tb1;      // terminals [tb0, tb1) of the current Gram batch
   int cell_budget;  // grid cells a thread-per-terminal search visits before handing off
+  int single;       // this round's clusters are all single points and the search wrote t_best
   double *tile_v;
   long long pair_cap, tile_cap;
   int cell_cap;

@@ -3269,7 +3269,7 @@ __global__ void k_chain(State S) {
       continue;
     }
     const int u = (int)(key & 0xffffffffu);
-    const double v = (centroid_link(S.linkage) && !S.gram) ? S.t_best[ti] : pos_from_bits(S.t_min[ti]);
+    const double v = ((centroid_link(S.linkage) || S.single) && !S.gram) ? S.t_best[ti] : pos_from_bits(S.t_min[ti]);
     const double h = key_to_height(S.linkage, v);
     S.succ[t] = u;
     S.succ_node[t] = S.node[u];
@@ -3722,6 +3722,7 @@ void launch_init(State &S, const float *x, hipStream_t s) {
 // complete; complete/average up to the emitted pair list and its tile prefix).
 void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs) {
   const int gb = nblk(nact, 2048);
+  S.single = 0;
   k_reset_round<<<1, 1, 0, s>>>(S.cnt);
   k_act_pass<<<gb, kBlock, 0, s>>>(S, round);
   scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, &S.cnt->n_term, S.part, s);
@@ -3748,6 +3749,16 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
     k_term_pos<<<gb, kBlock, 0, s>>>(S);
     if (S.linkage == kWard) launch_tree_search<kWard>(S, nact, s);
     else launch_tree_search<kAvgSq>(S, nact, s);
+    return;
+  }
+  // Round 0 of complete linkage: every cluster is one point, where the
+  // complete key (largest squared point distance) is the squared distance and
+  // so is the Ward key (weight 2*1*1/(1+1) = 1, exact), summed in the same
+  // order with the same tie-break: Ward's lighter search gives the same
+  // neighbours and values, and no pair needs evaluating.
+  S.single = (round == 0 && S.linkage == kComplete && S.d <= kGridMaxDim && S.prune) ? 1 : 0;
+  if (S.single) {
+    launch_search<kWard>(S, nact, s, t_ovf);
     return;
   }
   switch (S.linkage) {
