@@ -335,3 +335,45 @@ def test_box_tree_equals_other_searches(pc, link, d, kind, monkeypatch):
     Zr, cert = oracle.nnchain(x, link, threads=8)
     if cert["min_gap"] >= 1e-10:
         assert _trees.same_tree(Zt, Zr, n, rtol=RTOL[link])
+
+
+@pytest.mark.parametrize("link", ["ward", "avgsq"])
+@pytest.mark.parametrize("d", [3, 5])
+def test_box_tree_edge_cases(pc, link, d, monkeypatch):
+    """The box tree in every round on tiny inputs (one partial leaf, leaves
+    across one level), duplicated points (zero keys, ties broken by cluster
+    ID) and all-equal points; rows against the oracle."""
+    monkeypatch.setenv("PC_TREE_GRAM_SWITCH", "0")
+    for n in (2, 3, 17, 16 * 16 + 1, 700):
+        x = synth.uniform(n, d, 90 + n)
+        Zo, cert = oracle.nnchain(x, link)
+        Z = pc.hac(x, link)
+        _trees.assert_valid(Z, n)
+        if cert["min_gap"] >= 1e-10:
+            assert _trees.same_tree(Z, Zo, n, rtol=RTOL[link]), (n, d)
+    x = synth.uniform(300, d, 99)
+    x[150:] = x[:150]  # every point twice
+    Z = pc.hac(x, link)
+    _trees.assert_valid(Z, 300)
+    assert np.all(Z[:150, 2] == 0.0)
+    assert {frozenset((int(a), int(b))) for a, b in Z[:150, :2]} == {frozenset((i, i + 150)) for i in range(150)}
+    Z = pc.hac(np.ones((40, d), np.float32), link)
+    assert np.all(Z[:, 2] == 0.0)
+
+
+@pytest.mark.parametrize("d", [5, 8, 12])
+def test_complete_giant_pairs_block_pruning(pc, d):
+    """Two large blobs far apart (d <= 16): the last merges join clusters of
+    thousands of points, whose interval tiles are pruned by block boxes; the
+    rows must match the oracle exactly."""
+    rng = np.random.default_rng(100 + d)
+    a = rng.normal(0.0, 1.0, (2500, d))
+    b = rng.normal(0.0, 1.0, (2000, d)) + 6.0
+    x = np.vstack([a, b]).astype(np.float32)
+    Zo, cert = oracle.nnchain(x, "complete", threads=8)
+    Z, st = pc.hac(x, "complete", return_stats=True)
+    assert st["kernels"]["block_search"]["visits"] > 0  # point pairs screened
+    if cert["min_gap"] >= 1e-10:
+        assert _trees.same_tree(Z, Zo, x.shape[0], rtol=0.0)
+    C = oracle.canonical(Zo, x.shape[0])
+    assert Z[-1, 2] == C[-1, 2]  # the farthest pair of the final merge, bit for bit
