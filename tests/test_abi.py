@@ -43,7 +43,14 @@ def test_workspace_bytes_validation():
     assert pc.workspace_bytes(0, 2, "ward") == 0
     assert pc.workspace_bytes(10, 0, "ward") == 0
     assert pc.workspace_bytes(10, 2, 7) == 0
+    assert pc.workspace_bytes(10, 2, 4) == 0  # one past the last linkage (avg-2 = 3)
+    assert pc.workspace_bytes(10, 2, -1) == 0
     assert pc.workspace_bytes(2**31, 2, "ward") == 0
+    # every linkage, including avg-2, has a footprint; avg-2 keeps no points,
+    # like Ward, so at d = 3 (box tree) it needs far less than complete
+    for link in ("complete", "average", "ward", "avgsq"):
+        assert pc.workspace_bytes(100_000, 3, link) > 0
+    assert pc.workspace_bytes(100_000, 3, "avgsq") < pc.workspace_bytes(100_000, 3, "complete")
     a = pc.workspace_bytes(1000, 2, "ward")
     b = pc.workspace_bytes(2000, 2, "ward")
     assert 0 < a < b
