@@ -78,8 +78,9 @@ typedef struct {
                           on the call's stream (fills the kernel_* stats) */
     int32_t cache_slots; /* cluster-pair distance cache (Alg. 4, Sec. 5):
                           capacity ~ cache_slots * n entries; -1 = default
-                          (64 for average, 0 = off for complete and Ward,
-                          the paper's settings) */
+                          (64 for average, 0 = off for complete, the paper's
+                          settings; Ward and avg-2 values are O(1) from
+                          centroids and never use it) */
     int32_t reserved;
 } pc_options;
 
@@ -98,9 +99,11 @@ typedef struct {
     double ms_finalize;       /* sort rows + relabel */
     /* with pc_options.timing: summed device time and launch count of the
      * search/evaluation kernels (HIP events around each launch) */
-    double kernel_ms[4];      /* [0] ring search (bound pass), [1] block ring
-                                 search / full scan, [2] pair tiles,
-                                 [3] ring search (pair emission pass) */
+    double kernel_ms[4];      /* [0] search: ring search (bound pass), box-tree
+                                 search or Gram pass 0; [1] block ring search,
+                                 full scan or interval tiles; [2] exact pair
+                                 tiles; [3] ring search (pair emission pass) or
+                                 Gram pass 1 with exact candidate values */
     int64_t kernel_launches[4];
     int64_t candidate_visits[4]; /* candidate clusters examined, per kernel above */
     int64_t cache_hits;       /* pair distances reused from the cache */
