@@ -2838,6 +2838,75 @@ __global__ void k_cand_triage(State S, int ncand) {
 
 __global__ void k_scr_count(Counters *c) { c->n_scr32 = (int)c->n_scr; }
 
+// Complete, d <= kBlkMaxDim: a tighter fixed bound for each large screened
+// candidate before its tiles, from real point pairs found by farthest-point
+// steps (one block per candidate): the row point farthest from the column
+// cluster's centroid, the column point farthest from it, and the row point
+// farthest from that. Their squared distances are keys of real pairs, so the
+// largest is a lower bound of the candidate's key (lowered by 1e-12 for the
+// summation order).
+constexpr long long kSeedTiles = 16;  // candidates with fewer tiles keep L0
+
+// the point of [beg, beg + cnt) farthest from ref (FP32 distance picks it)
+__device__ int far_point(const State &S, int beg, int cnt, const double *ref) {
+  const int d = S.d;
+  unsigned long long best = 0;
+  for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+    const float *x = S.px + (size_t)(beg + j) * d;
+    double q = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const double u = (double)x[k] - ref[k];
+      q += u * u;
+    }
+    const unsigned long long key = ((unsigned long long)__float_as_uint((float)q) << 32) | (unsigned)j;
+    best = key > best ? key : best;
+  }
+  best = block_reduce<unsigned long long, false>(best);
+  return beg + (int)(best & 0xffffffffu);
+}
+
+__device__ __forceinline__ double point_sq(const State &S, int a, int b) {
+  const int d = S.d;
+  double q = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double u = (double)S.px[(size_t)a * d + k] - (double)S.px[(size_t)b * d + k];
+    q += u * u;
+  }
+  return q;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cand_seed(State S) {
+  __shared__ double ref[kBlkMaxDim];
+  const int nscr = S.cnt->n_scr32, d = S.d;
+  for (int k = blockIdx.x; k < nscr; k += gridDim.x) {
+    const int4 ds = S.cd_desc[k];
+    const long long tiles = (long long)((ds.y + kGT - 1) / kGT) * ((ds.w + kGT - 1) / kGT);
+    if (tiles < kSeedTiles) continue;  // uniform per block
+    const int i = S.cd_scr[k];
+    const int c = S.cd_c[i];
+    __syncthreads();
+    if (threadIdx.x < d) ref[threadIdx.x] = S.wcen[(size_t)c * d + threadIdx.x];
+    __syncthreads();
+    const int r1 = far_point(S, ds.x, ds.y, ref);
+    __syncthreads();
+    if (threadIdx.x < d) ref[threadIdx.x] = (double)S.px[(size_t)r1 * d + threadIdx.x];
+    __syncthreads();
+    const int c1 = far_point(S, ds.z, ds.w, ref);
+    __syncthreads();
+    if (threadIdx.x < d) ref[threadIdx.x] = (double)S.px[(size_t)c1 * d + threadIdx.x];
+    __syncthreads();
+    const int r2 = far_point(S, ds.x, ds.y, ref);
+    if (threadIdx.x == 0) {
+      const double a = point_sq(S, r1, c1), b = point_sq(S, r2, c1);
+      const double l = (a > b ? a : b) * (1.0 - 1e-12);
+      if (l > S.cd_l0[k]) {
+        S.cd_l0[k] = l;
+        if (l > S.cd_lb[i]) S.cd_lb[i] = l;
+      }
+    }
+  }
+}
+
 // Small candidates: a wavefront per candidate, a lane per point pair (rows:
 // the cluster with the lower ID), coordinates summed in order; points are
 // read in 16-byte pieces when d is a multiple of 4.
@@ -3604,6 +3673,7 @@ void launch_gram_refine_t(State &S, int ncand, hipStream_t s) {
     k_cand_triage<LINK><<<nblk(ncand, 4096), kBlock, 0, s>>>(S, ncand);
     k_cand_small<LINK><<<8192, kBlock, 0, s>>>(S);
     k_scr_count<<<1, 1, 0, s>>>(S.cnt);
+    if (LINK == kComplete && S.d <= kBlkMaxDim) k_cand_seed<<<2048, kBlock, 0, s>>>(S);
     scan_exclusive_i64(S.cd_tile0, S.cd_tile0, ncand, &S.cnt->n_scr32, &S.cnt->n_ctiles, S.part, s);
     tmark(S, 1, false, s);  // the interval tiles alone
     switch (S.gkp) {
