@@ -15,10 +15,12 @@ Also reported (one JSON line):
                 timed on this host's cores on a bounded sample of the same law
 Extra, outside the timed steps: the 10,000,000-point Ward run of the same law;
 one run each of the d = 10 (1M uniform, average) and d = 128 (200K unit
-vectors, Ward / complete / average) workloads with their dominant kernel's
-roofline; one run each on the paper's own synthetic laws (2U1M, 2G1M, 5U1M,
-5G1M, 2U10M, 2G10M) beside its 48-core times; the serving leg (a trace of requests of uneven n, d and linkage:
-one at a time, open loop with p50/p99 latency, all at once).
+vectors, Ward / complete / average / avg-2) workloads with their dominant
+kernel's roofline; one run each on the paper's own synthetic laws (2U1M, 2G1M,
+5U1M, 5G1M, 2U10M, 2G10M) beside its 48-core times; the serving leg (a trace of
+requests of uneven n, d and linkage: one at a time, open loop with p50/p99
+latency, all at once). With --ablations: range-query pruning on / off and the
+cluster-pair cache size (0, 16, 64, 256 slots per cluster).
 """
 from __future__ import annotations
 
@@ -77,6 +79,14 @@ def roofline(kname, link, d, ms, nl, sts):
         achieved = work / (avg_ms / 1000.0) / 1e12
         r = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VEC_TFLOPS, "unit": "TFLOP/s",
              "note": "exact FP64 point-pair tiles; work = point pairs x FP64 flops per pair"}
+    elif link in ("ward", "avgsq") and 3 <= d <= 5 and kname == "ring_search":
+        # the box-tree walk (the rounds with many active clusters; later rounds'
+        # Gram pass 0 shares the timing slot but takes a small part of it):
+        # a gather kernel, one visit = a candidate record or a node box
+        work = visits * visit_bytes(link, d) / nl
+        achieved = work / (avg_ms / 1000.0) / 1e9
+        r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+             "note": "box-tree search: visits x record bytes (the slot also holds Gram pass 0 rounds)"}
     elif gram and kname in ("ring_search", "ring_emit", "block_search"):
         # Gram passes (centroid pairs) and interval tiles (point pairs): FP16 MFMA,
         # 2 x K flops per pair

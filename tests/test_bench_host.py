@@ -1,0 +1,70 @@
+"""Host-side pieces of bench.py (no GPU): the MFMA depth table, the per-visit
+byte prices, the roofline arithmetic, the traffic lookup with its source-hash
+check, and the one-GPU refusal."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_gram_depth_covers_d_plus_two():
+    for d in range(1, 129):
+        kp = bench.gram_kp(d)
+        assert kp % 16 == 0 and kp >= d + 2
+    assert [bench.gram_kp(d) for d in (2, 14, 15, 30, 62, 78, 126, 127)] == [16, 16, 32, 32, 64, 80, 128, 144]
+
+
+def test_visit_prices():
+    # 16 B record + FP64 centroid; avg-2 adds its FP64 spread term,
+    # complete / average the FP32 box
+    assert bench.visit_bytes("ward", 2) == 32
+    assert bench.visit_bytes("avgsq", 2) == 40
+    assert bench.visit_bytes("complete", 2) == 48
+    assert bench.visit_bytes("average", 5) == 16 + 40 + 40
+
+
+def test_roofline_arithmetic():
+    st = {"kernels": {"ring_search": {"visits": 1_000_000}}, "point_pair_evals": 0}
+    # 2 launches taking 1 ms in total: 1e6 visits x 48 B / 2 launches = 24 MB
+    # per launch in 0.5 ms = 48 GB/s
+    r = bench.roofline("ring_search", "complete", 2, 1.0, 2, [st])
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert r["achieved"] == pytest.approx(48.0)
+    assert r["frac"] == pytest.approx(48.0 / bench.PEAK_HBM_GBS)
+    assert r["work_per_launch"] == pytest.approx(24e6)
+    # a Gram-search kernel at d = 10 is priced as FP16 MFMA work: 2K flops per pair
+    r = bench.roofline("ring_search", "ward", 10, 1.0, 1, [st])
+    assert r["bound"] == "mfma" and r["achieved"] == pytest.approx(1e6 * 2 * 16 / 1e-3 / 1e12)
+    # the box-tree walk (Ward / avg-2, 3 <= d <= 5) is a gather kernel
+    r = bench.roofline("ring_search", "avgsq", 5, 1.0, 1, [st])
+    assert r["bound"] == "hbm" and r["work_per_launch"] == pytest.approx(1e6 * bench.visit_bytes("avgsq", 5))
+
+
+def test_traffic_lookup_follows_the_kernel_source():
+    path = os.path.join(ROOT, "profiles", "blob50_1m_d2_complete_ring_search_traffic.md")
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    src = os.path.join(ROOT, "paper_2106_04727_amd", "csrc", "pc_round.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    got = bench.measured_traffic("ring_search", "complete", 2)
+    if vals["kernel_source_sha256"] == sha:
+        assert got == float(vals["hbm_bytes_per_launch"])
+    else:
+        assert got is None  # counters taken on other kernel code are not reported
+    assert bench.measured_traffic("ring_search", "complete", 10) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
