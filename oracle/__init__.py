@@ -6,9 +6,12 @@ library never imports, loads or calls anything here, and this package imports
 nothing from the library.
 
 Contents
-  * ``nnchain``       sequential nearest-neighbour chain in FP64 (C, ``nnchain.c``)
+  * ``nnchain``       sequential nearest-neighbour chain in FP64 (C, ``nnchain.c``);
+                      ``accel=True`` answers its queries through a centroid grid
+                      with exact pruning (same rows, bit for bit)
   * ``linkage_dist``  linkage distance of two explicit member sets (Table 1)
-  * ``canonical``     the dendrogram row convention (sorted rows, scipy ids)
+  * ``canonical``     the dendrogram row convention (sorted rows, scipy ids);
+                      ``canonical_fast`` is the same rule in C for large n
   * ``brute``         generic HAC by brute force, for tiny inputs (``brute.py``)
 
 Linkage codes: 0 complete, 1 average (mean Euclidean, avg-1), 2 Ward,
@@ -58,6 +61,15 @@ def _load():
             ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
             i64p, i64p, f64p, i64p, f64p,
         ]
+        lib.oracle_nnchain_grid.restype = ctypes.c_int
+        lib.oracle_nnchain_grid.argtypes = [
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+            i64p, i64p, f64p, i64p, f64p,
+        ]
+        lib.oracle_canonical.restype = ctypes.c_int
+        lib.oracle_canonical.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        lib.oracle_merge_keys.restype = ctypes.c_int
+        lib.oracle_merge_keys.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
         lib.oracle_tree_sums.restype = ctypes.c_int
         lib.oracle_tree_sums.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]
@@ -77,7 +89,12 @@ def _ptr(a, t):
     return a.ctypes.data_as(ctypes.POINTER(t))
 
 
-def nnchain(x: np.ndarray, linkage, threads: int = 0):
+# Accelerated mode reports min(plain mode's min_gap, GAP_CAP): candidates it
+# skips exceed the best by more than that relative gap.
+GAP_CAP = 2.0 ** -23
+
+
+def nnchain(x: np.ndarray, linkage, threads: int = 0, accel: bool = False):
     """Sequential NN-chain HAC of float32 points ``x`` (n, d).
 
     Returns ``(Z, cert)``: ``Z`` is (n-1, 4) float64 rows in merge order
@@ -85,6 +102,11 @@ def nnchain(x: np.ndarray, linkage, threads: int = 0):
     ``cert`` holds the tie certificate: ``min_gap`` (smallest relative gap
     between best and runner-up over all queries), ``zero_best``, ``queries``
     and ``pair_evals``.
+
+    ``accel=True``: the same chain with grid-pruned queries (single thread);
+    the rows are those of plain mode bit for bit, ``min_gap`` is
+    ``min(plain min_gap, GAP_CAP)`` and ``pair_evals`` counts the point pairs
+    actually evaluated (``cand_evals`` the candidate clusters examined).
     """
     x = np.ascontiguousarray(x, dtype=np.float32)
     n, d = x.shape
@@ -93,17 +115,20 @@ def nnchain(x: np.ndarray, linkage, threads: int = 0):
     b = np.zeros(m, np.int64)
     h = np.zeros(m, np.float64)
     s = np.zeros(m, np.int64)
-    cert = np.zeros(4, np.float64)
-    rc = _load().oracle_nnchain(
-        x.ctypes.data, n, d, _code(linkage), int(threads),
-        _ptr(a, ctypes.c_int64), _ptr(b, ctypes.c_int64), _ptr(h, ctypes.c_double),
-        _ptr(s, ctypes.c_int64), _ptr(cert, ctypes.c_double),
-    )
+    cert = np.zeros(6, np.float64)
+    ptrs = (_ptr(a, ctypes.c_int64), _ptr(b, ctypes.c_int64), _ptr(h, ctypes.c_double),
+            _ptr(s, ctypes.c_int64), _ptr(cert, ctypes.c_double))
+    if accel:
+        rc = _load().oracle_nnchain_grid(x.ctypes.data, n, d, _code(linkage), *ptrs)
+    else:
+        rc = _load().oracle_nnchain(x.ctypes.data, n, d, _code(linkage), int(threads), *ptrs)
     if rc != 0:
         raise ValueError("oracle_nnchain failed with code %d" % rc)
     Z = np.stack([a, b, h, s], axis=1).astype(np.float64)[: n - 1]
-    return Z, dict(min_gap=cert[0], zero_best=int(cert[1]), queries=int(cert[2]),
-                   pair_evals=int(cert[3]))
+    out = dict(min_gap=cert[0], zero_best=int(cert[1]), queries=int(cert[2]), pair_evals=int(cert[3]))
+    if accel:
+        out.update(cand_evals=int(cert[4]), grid_rebuilds=int(cert[5]))
+    return Z, out
 
 
 def linkage_dist(x: np.ndarray, linkage, A, B) -> float:
@@ -150,6 +175,34 @@ def members(Z: np.ndarray, n: int):
         a, b = int(Z[r, 0]), int(Z[r, 1])
         mem[n + r] = mem[a] + mem[b]
     return mem
+
+
+def canonical_fast(Z: np.ndarray, n: int) -> np.ndarray:
+    """``canonical`` for large row counts (C; the same rule, tested equal)."""
+    m = n - 1
+    if m <= 0:
+        return np.zeros((0, 4), np.float64)
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    out = np.zeros((m, 4), np.float64)
+    rc = _load().oracle_canonical(Z.ctypes.data, n, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("rows are not a valid creation order (%d)" % rc)
+    return out
+
+
+def merge_keys(Z: np.ndarray, n: int) -> np.ndarray:
+    """Every merge of dendrogram ``Z`` as int64 (lo_a, size_a, lo_b, size_b):
+    its children identified by lowest point index and size (smaller pair
+    first), rows in the order of ``Z``."""
+    m = n - 1
+    if m <= 0:
+        return np.zeros((0, 4), np.int64)
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    out = np.zeros((m, 4), np.int64)
+    rc = _load().oracle_merge_keys(Z.ctypes.data, n, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("rows are not a valid creation order (%d)" % rc)
+    return out
 
 
 def canonical(Z: np.ndarray, n: int) -> np.ndarray:

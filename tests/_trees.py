@@ -65,3 +65,32 @@ def max_rel_height_err(Z1, Z2, n):
         if den > 0:
             err = max(err, abs(h - h2) / den)
     return err
+
+
+def assert_valid_hac(x, Z, link, rtol=1e-12):
+    """Validity of a dendrogram on inputs with ties (several dendrograms are
+    then correct): in the row order given (a creation order), each merge's
+    height is the linkage distance of its two children, and no cluster alive
+    at that time is closer to either child than that height, i.e. the two
+    were reciprocal nearest neighbours when they merged. Distances come from
+    the oracle's definitions over explicit member sets (tiny inputs only)."""
+    import oracle
+
+    Z = np.asarray(Z)
+    n = Z.shape[0] + 1
+    assert_valid(Z, n)
+    mem = {i: np.array([i], np.int64) for i in range(n)}
+    alive = set(range(n))
+    for r in range(n - 1):
+        a, b, h = int(Z[r, 0]), int(Z[r, 1]), float(Z[r, 2])
+        d_ab = oracle.linkage_dist(x, link, mem[a], mem[b])
+        assert abs(d_ab - h) <= rtol * max(abs(h), abs(d_ab)), (r, h, d_ab)
+        for c in alive:
+            if c in (a, b):
+                continue
+            for v in (a, b):
+                d = oracle.linkage_dist(x, link, mem[v], mem[c])
+                assert d >= h * (1.0 - rtol), (r, v, c, d, h)
+        alive -= {a, b}
+        alive.add(n + r)
+        mem[n + r] = np.concatenate([mem[a], mem[b]])
