@@ -11,16 +11,17 @@ Also reported (one JSON line):
   roofline      the step's dominant kernel, measured live with HIP events on
                 the library's stream: algorithmic work per launch / average
                 launch time, against MI355X's published peak
-  cpu_baseline  the FP64 oracle (sequential NN-chain, OpenMP candidate scan)
-                timed on this host's cores on a bounded sample of the same law
+  cpu_baseline  the FP64 oracle (sequential NN-chain, accelerated mode) timed
+                on this host on the first points of the same input
 Extra, outside the timed steps: the 10,000,000-point Ward run of the same law;
 one run each of the d = 10 (1M uniform, average) and d = 128 (200K unit
 vectors, Ward / complete / average / avg-2) workloads with their dominant
 kernel's roofline; one run each on the paper's own synthetic laws (2U1M, 2G1M,
-5U1M, 5G1M, 2U10M, 2G10M) beside its 48-core times; the serving leg (a trace of
-requests of uneven n, d and linkage: one at a time, open loop with p50/p99
-latency, all at once). With --ablations: range-query pruning on / off and the
-cluster-pair cache size (0, 16, 64, 256 slots per cluster).
+5U1M, 5G1M, 2U10M, 2G10M) beside its 48-core times; range-query pruning on /
+off and the cluster-pair cache size (0, 16, 64, 256 slots per cluster); the
+serving leg (a trace of requests of uneven n, d and linkage: one at a time,
+open loop at 0.8 x the one-at-a-time capacity with p50/p99 latency, all at
+once).
 """
 from __future__ import annotations
 
@@ -38,16 +39,16 @@ PEAK_FP64_VEC_TFLOPS = 78.6
 PEAK_FP16_MFMA_TFLOPS = 2500.0
 
 # Algorithmic unit costs.
-#   search kernels: per candidate visited, its 16-byte (slot, size, cid) record
-#   and FP64 centroid (8 d bytes), plus the float32 box (8 d bytes) for
-#   complete/average; the kernels are gathers, so they are priced against HBM
-#   bandwidth.
+#   search kernels: per candidate visited, the fields a range query has to
+#   read: the FP64 centroid (8 d bytes), size and cluster ID (4 + 4 bytes),
+#   plus the float32 box (8 d bytes) for complete / average and the FP64
+#   spread term (8 bytes) for avg-2; the kernels are gathers, so they are
+#   priced against HBM bandwidth (40 bytes per visit for complete at d = 2,
+#   24 for Ward).
 #   complete tiles: 6 FP64 flops per point pair at d = 2 (2 sub, 2 mul, 1 add,
 #   1 max), priced against the FP64 vector peak.
 def visit_bytes(link, d=2):
-    # meta (slot, size, cid, spread) + FP64 centroid; avg-2 adds its spread
-    # term, complete/average the FP32 box
-    return 16 + 8 * d + {"ward": 0, "avgsq": 8}.get(link, 8 * d)
+    return 8 * d + 4 + 4 + {"ward": 0, "avgsq": 8}.get(link, 8 * d)
 
 
 COMPLETE_PAIR_FLOPS = 6
@@ -101,6 +102,10 @@ def roofline(kname, link, d, ms, nl, sts):
              "note": "search kernels gather candidate records; work = visits x record bytes"}
     r["frac"] = r["achieved"] / r["peak"]
     r["traffic"] = measured_traffic(kname, link, d)
+    if r["traffic"] is not None and r["unit"] == "GB/s":
+        # the same launches priced by the HBM bytes the counters measured
+        r["measured_gbs"] = r["traffic"] / (avg_ms / 1000.0) / 1e9
+        r["measured_frac"] = r["measured_gbs"] / PEAK_HBM_GBS
     r.update({"kernel": kname, "linkage": link, "avg_launch_ms": avg_ms, "launches": nl,
               "work_per_launch": work})
     return r
@@ -249,7 +254,9 @@ def serve_bench(num, slots, n_max):
                 out_on_device=False)
     t_seq = time.perf_counter() - t0
     ctx.close()
-    span = 0.8 * t_seq
+    # arrival rate 0.8 x the measured one-at-a-time capacity
+    rate = 0.8 * num / t_seq
+    span = num / rate
     scale = span / max(trace[-1]["t"], 1e-9)
     arrivals = [r["t"] * scale for r in trace]
     lat = []
@@ -284,7 +291,7 @@ def serve_bench(num, slots, n_max):
         "trace": "Poisson arrivals; n log-uniform [256, n_max], d uniform {2,3,10,64}, linkage uniform "
                  "{complete, average, ward}, 5-100 Gaussian blobs, sigma 0.01-0.05 (seed 41)",
         "one_at_a_time_s": t_seq, "one_at_a_time_req_per_s": num / t_seq,
-        "offered_rate_req_per_s": num / span,
+        "offered_rate_req_per_s": num / span, "offered_load_vs_capacity": 0.8,
         "open_loop_makespan_s": makespan,
         "burst_makespan_s": burst_s, "burst_req_per_s": num / burst_s,
         "burst_speedup_vs_one_at_a_time": t_seq / burst_s,
@@ -302,17 +309,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=100_000,
+                    help="points of the headline input the CPU oracle baseline clusters")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 10M Ward run and the d=10 / d=128 workloads")
     ap.add_argument("--links", default=",".join(LINKS))
-    ap.add_argument("--serve-requests", type=int, default=40,
+    ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the serving trace (0 skips the serving leg)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-nmax", type=int, default=200_000)
     ap.add_argument("--workload", default="blob50_1m_d2",
                     help="named input of synth.WORKLOADS (the headline is blob50_1m_d2)")
-    ap.add_argument("--ablations", action="store_true",
-                    help="also run the pruning on/off and cache-size ablations")
+    ap.add_argument("--no-ablations", action="store_true",
+                    help="skip the pruning on/off and cache-size ablations")
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy 256 MiB on the device first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -436,7 +445,7 @@ def main():
 
     if not args.no_extra and args.workload == "blob50_1m_d2":
         out["workloads"] = {}
-        for wl, link in (("u1m_d10", "average"), ("vmf1000_200k_d128", "ward"),
+        for wl, link in (("u1m_d10", "average"), ("blob100_1m_d10", "average"), ("vmf1000_200k_d128", "ward"),
                          ("vmf1000_200k_d128", "complete"), ("vmf1000_200k_d128", "average"),
                          ("vmf1000_200k_d128", "avgsq")):
             try:
@@ -447,7 +456,7 @@ def main():
     if not args.no_extra and args.workload == "blob50_1m_d2":
         out["paper_sets"] = paper_leg(pc, synth, torch, ctx, stream)
 
-    if args.ablations:
+    if not args.no_ablations and args.workload == "blob50_1m_d2":
         try:
             out["ablations"] = ablation_leg(pc, synth, torch, ctx, stream)
         except Exception as e:  # reported, never hidden
@@ -462,22 +471,24 @@ def main():
     if not args.no_cpu:
         import oracle
 
+        # the FP64 oracle (sequential NN-chain, accelerated mode: grid-pruned
+        # exact queries) on the first points of the headline input itself
         cores = os.cpu_count() or 1
-        samples = [("ward", 40_000), ("complete", 12_000)]
-        tt, pts = 0.0, 0
-        detail = {}
-        for link, m in samples:
-            xs = synth.blobs(m, 2, 50, 0.01, 11)
+        m = min(args.cpu_sample, n)
+        xs = np.ascontiguousarray(x[:m])
+        tt, detail = 0.0, {}
+        for link in links:
             t = time.perf_counter()
-            oracle.nnchain(xs, link, threads=cores)
+            _, cert = oracle.nnchain(xs, link, accel=True)
             dt = time.perf_counter() - t
             tt += dt
-            pts += m
-            detail[link] = {"n": m, "s": dt}
+            detail[link] = {"n": m, "s": dt, "points_per_s": m / dt, "cand_evals": cert["cand_evals"],
+                            "point_pair_evals": cert["pair_evals"]}
         out["cpu_baseline"] = {
-            "value": pts / tt, "unit": "points/s", "cores": cores, "kind": "oracle",
-            "sample": "FP64 NN-chain oracle on the same 50-Gaussian law at n=40,000 (Ward) and "
-                      "n=12,000 (complete); its cost grows ~n^2, so at n=1M it is far slower",
+            "value": m * len(links) / tt, "unit": "points/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 NN-chain oracle (accelerated mode) on the first %d points of the headline "
+                      "input, %s linkage; the chain is sequential (one thread), only large complete-"
+                      "linkage pair maxima use the %d host threads" % (m, " + ".join(links), cores),
             "detail": detail,
         }
     print(json.dumps(out))

@@ -51,9 +51,24 @@ typedef enum {
                               mean; heights are in squared units */
 } pc_linkage;
 
+/*
+ * Precision of the screening tiles (Table 1 distances are what they bound).
+ * At 4 <= d <= 128 a round first compares every chain tail with every active
+ * cluster through matrix-core Gram tiles of rounded centroids, and large
+ * complete / average candidate pairs are bracketed by tiles over their point
+ * pairs; every candidate those tiles cannot rule out (by rigorous rounding
+ * bounds) is then evaluated in FP64. So in every mode every decision and
+ * every height comes from FP64 arithmetic on the float32 inputs, and the rows
+ * are the same; the modes differ in the tiles' element type, hence in speed
+ * and in how many candidates need the FP64 evaluation (pc_stats.refined).
+ * Below d = 4 (and above 128) no tiles are used and the modes coincide.
+ */
 typedef enum {
-    PC_PREC_EXACT = 0 /* every decision and height from FP64 arithmetic on the
-                         float32 inputs (FP32 inputs widened exactly) */
+    PC_PREC_FP16_REFINE = 0, /* FP16 operands, FP32 accumulate (default) */
+    PC_PREC_BF16_REFINE = 1, /* BF16 operands, FP32 accumulate */
+    PC_PREC_FP32 = 2,        /* FP32 operands and accumulate (the FP32
+                                matrix-core instruction) */
+    PC_PREC_EXACT = PC_PREC_FP16_REFINE
 } pc_precision;
 
 /* One dendrogram row, scipy linkage-matrix convention: leaves are 0..n-1,
@@ -70,7 +85,7 @@ typedef struct {
 /* Options; pass NULL for defaults. struct_size must be sizeof(pc_options). */
 typedef struct {
     uint32_t struct_size;
-    int32_t precision; /* pc_precision, default PC_PREC_EXACT */
+    int32_t precision; /* pc_precision, default PC_PREC_FP16_REFINE */
     int32_t prune;     /* 1 (default): range-query pruning (Sec. 4);
                           0: every terminal scans every active cluster
                           (same result, for ablations and tests) */
@@ -111,6 +126,16 @@ typedef struct {
     int64_t cache_fail;       /* stores dropped because the probe window was full */
     int64_t cache_derived;    /* pair values combined from cached parts
                                  (Lance-Williams rules, Table 2 / Sec. 5) */
+    int64_t refined;          /* candidates the screening tiles could not rule
+                                 out, then given their exact FP64 value */
+    int64_t fp64_fallbacks;   /* of those, the ones beyond one per screened
+                                 chain tail: FP64 work owed to the tiles'
+                                 error bounds */
+    /* with pc_options.timing: device time of the rounds by phase */
+    double ms_nn;             /* terminals, spatial index, nearest-neighbour
+                                 search and candidate evaluation */
+    double ms_merge;          /* chain update, reciprocal pairs, merges */
+    double ms_update;         /* active set and point-range compaction */
 } pc_stats;
 
 typedef struct pc_context pc_context;
@@ -119,9 +144,12 @@ typedef struct pc_context pc_context;
  * Create a context on HIP device `device` (the caller's current device if
  * device < 0). The context owns the device workspace, grown on demand and
  * reused across calls; it is not thread-safe (concurrent calls on one
- * context return PC_ERR_BUSY).
+ * context return PC_ERR_BUSY). hbm_budget_bytes > 0 caps the device bytes
+ * the context may hold: a call whose workspace would exceed it runs the Gram
+ * search's chain tails in smaller batches where it can, and otherwise fails
+ * with PC_ERR_OUT_OF_MEMORY (the context keeps what it held). 0: no cap.
  */
-pc_status pc_context_create(int device, pc_context **out);
+pc_status pc_context_create(int device, size_t hbm_budget_bytes, pc_context **out);
 void pc_context_destroy(pc_context *ctx);
 
 /* Device bytes pc_hac needs for (n, d, linkage); 0 on bad arguments. */
@@ -150,16 +178,22 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
  * A server keeps up to `slots` requests on the GPU at once, each on its own
  * context and HIP stream, so the rounds of different requests overlap on the
  * device; requests that arrive while others run are admitted as slots and
- * memory free up (continuous batching of whole requests). Admission: a
- * request's device footprint is pc_hac_workspace_bytes(n, d, linkage, opt)
- * (the initial workspace; record buffers can grow beyond it during a run),
- * and a request starts when a slot is free and its footprint fits in the
- * budget left by the running ones. Waiting requests are taken in arrival
- * order; a later request that fits may start before an earlier one that does
- * not (first fit), until the earlier one has been passed over 16 times.
- * A request whose footprint exceeds the whole budget is refused at submission
- * with PC_ERR_OUT_OF_MEMORY. A request's rows are those pc_hac computes for
- * the same input, whatever else runs. All server functions are thread-safe.
+ * memory free up (continuous batching of whole requests). Admission: device
+ * bytes are accounted per slot, an idle slot counting what its context kept
+ * from earlier requests and a busy one its request's reservation (at least
+ * that). A request's reservation starts at pc_hac_workspace_bytes(n, d,
+ * linkage, opt); it starts when a slot is free and the bytes it adds fit in
+ * the budget. While it runs, its context may not hold more than the
+ * reservation; a request that needs more (its candidate records grow with
+ * the data) goes back to the head of the queue with twice the reservation
+ * (counted in pc_server_stats.requeued) and fails with PC_ERR_OUT_OF_MEMORY
+ * once that would exceed the whole budget. So the bytes in use never exceed
+ * the budget. Waiting requests are taken in arrival order; a later request
+ * that fits may start before an earlier one that does not (first fit), until
+ * the earlier one has been passed over 16 times. A request whose footprint
+ * exceeds the whole budget is refused at submission with
+ * PC_ERR_OUT_OF_MEMORY. A request's rows are those pc_hac computes for the
+ * same input, whatever else runs. All server functions are thread-safe.
  */
 typedef struct pc_server pc_server;
 
@@ -170,6 +204,8 @@ typedef struct {
     double fake_us_per_kpoint;  /* test hook: > 0 runs no device work at all; a request then
                                    occupies its slot for this many microseconds per 1000
                                    points and its rows are zero (host-only tests of admission) */
+    double fake_growth;         /* test hook (with fake_us_per_kpoint): a request needs its
+                                   footprint times this many bytes (<= 0 selects 1) */
 } pc_server_options;
 
 typedef struct {
@@ -189,6 +225,7 @@ typedef struct {
     int64_t submitted, completed, rejected, cancelled, failed;
     int32_t running, queued, peak_running, reserved;
     uint64_t budget_bytes, bytes_in_use, peak_bytes_in_use;
+    int64_t requeued;         /* requests sent back to the queue with a larger reservation */
 } pc_server_stats;
 
 /* Create a server on HIP device `device` (current device if < 0); opt may be

@@ -46,7 +46,7 @@ struct Carver {
   }
 };
 
-size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_points,
+size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_points, int elem,
               float **xin = nullptr, pc_merge **rows_out = nullptr) {
   Carver c{base};
   const size_t n = (size_t)n64;
@@ -101,9 +101,11 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   const bool gram = d >= kGramMinDim && d <= kGramMaxDim;
   const int kp = gram_kp(d);
   S.gkp = kp;
-  S.g16 = c.take<_Float16>(gram ? n * kp : 1);
+  S.elem = elem;
+  const size_t ew = (size_t)screen_elem_bytes(elem) / 2;  // in 16-bit units
+  S.g16 = c.take<_Float16>(gram ? n * kp * ew : 1);
   S.gq = c.take<float4>(gram ? n : 1);
-  S.p16 = gram && pts ? c.take<_Float16>(n * kp) : nullptr;
+  S.p16 = gram && pts ? c.take<_Float16>(n * kp * ew) : nullptr;
   S.pq = c.take<float4>(gram && pts ? n : 1);
   const bool blk = gram && comp && d <= kBlkMaxDim;
   S.blk_lo = c.take<float>(blk ? (n / 64 + 2) * d : 1);
@@ -159,8 +161,39 @@ struct Buf {
   size_t bytes = 0;
 };
 
-hipError_t grow(Buf &b, size_t bytes) {
+}  // namespace
+
+struct pc_context {
+  int device = 0;
+  size_t budget = 0;         // most device bytes the context may hold (0: no limit)
+  bool over_budget = false;  // the last call stopped at the budget
+  Buf ws, pairs, tiles, part, fidx, cand, cache[2];
+  Counters *hcnt = nullptr;  // pinned host mirror of the device counters
+  hipEvent_t ev[4] = {};
+  hipEvent_t tev[8] = {};
+  hipEvent_t rev[4] = {};    // per round: start, search done, merge done, end
+  std::atomic<int> busy{0};
+};
+
+namespace {
+
+size_t held_bytes(const pc_context *c) {
+  size_t b = c->ws.bytes + c->pairs.bytes + c->tiles.bytes + c->part.bytes + c->fidx.bytes + c->cand.bytes;
+  return b + c->cache[0].bytes + c->cache[1].bytes;
+}
+
+// would growing b to `bytes` keep the context within its budget?
+bool fits(const pc_context *c, const Buf &b, size_t bytes) {
+  if (b.bytes >= bytes || !c->budget) return true;
+  return held_bytes(c) - b.bytes + bytes <= c->budget;
+}
+
+hipError_t grow(pc_context *c, Buf &b, size_t bytes) {
   if (b.bytes >= bytes) return hipSuccess;
+  if (!fits(c, b, bytes)) {
+    c->over_budget = true;  // b is left as it was
+    return hipErrorOutOfMemory;
+  }
   if (b.p) hipFree(b.p);
   b.p = nullptr;
   b.bytes = 0;
@@ -171,22 +204,13 @@ hipError_t grow(Buf &b, size_t bytes) {
 
 }  // namespace
 
-struct pc_context {
-  int device = 0;
-  Buf ws, pairs, tiles, part, fidx, cand, cache[2];
-  Counters *hcnt = nullptr;  // pinned host mirror of the device counters
-  hipEvent_t ev[4] = {};
-  hipEvent_t tev[8] = {};
-  std::atomic<int> busy{0};
-};
-
 extern "C" {
 
 const char *pc_last_error(void) { return g_err.c_str(); }
 
 const char *pc_version(void) { return "parchain-mi355x 0.1 (gfx950)"; }
 
-pc_status pc_context_create(int device, pc_context **out) {
+pc_status pc_context_create(int device, size_t hbm_budget_bytes, pc_context **out) {
   if (!out) return fail(PC_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   int dev = device;
@@ -198,10 +222,12 @@ pc_status pc_context_create(int device, pc_context **out) {
   pc_context *c = new (std::nothrow) pc_context();
   if (!c) return fail(PC_ERR_OUT_OF_MEMORY, "host allocation failed");
   c->device = dev;
+  c->budget = hbm_budget_bytes;
   hipError_t e = set_direction_table();
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hcnt, sizeof(Counters), hipHostMallocDefault);
   for (int i = 0; e == hipSuccess && i < 4; ++i) e = hipEventCreate(&c->ev[i]);
   for (int i = 0; e == hipSuccess && i < 8; ++i) e = hipEventCreate(&c->tev[i]);
+  for (int i = 0; e == hipSuccess && i < 4; ++i) e = hipEventCreate(&c->rev[i]);
   if (e != hipSuccess) {
     pc_context_destroy(c);
     return fail(PC_ERR_DEVICE, std::string("context setup: ") + hipGetErrorString(e));
@@ -218,10 +244,11 @@ void set_error(const char *msg) { g_err = msg; }
 
 // Device bytes a context holds, and release of its growable buffers (the
 // serving layer keeps each slot within its share of the budget).
-size_t context_bytes(const pc_context *c) {
-  size_t b = c->ws.bytes + c->pairs.bytes + c->tiles.bytes + c->part.bytes + c->fidx.bytes + c->cand.bytes;
-  return b + c->cache[0].bytes + c->cache[1].bytes;
-}
+size_t context_bytes(const pc_context *c) { return held_bytes(c); }
+
+// the serving layer caps a slot's context at the request's reservation
+void context_set_budget(pc_context *c, size_t bytes) { c->budget = bytes; }
+bool context_over_budget(const pc_context *c) { return c->over_budget; }
 
 void context_trim(pc_context *c) {
   hipSetDevice(c->device);
@@ -252,13 +279,16 @@ void pc_context_destroy(pc_context *c) {
     if (c->ev[i]) hipEventDestroy(c->ev[i]);
   for (int i = 0; i < 8; ++i)
     if (c->tev[i]) hipEventDestroy(c->tev[i]);
+  for (int i = 0; i < 4; ++i)
+    if (c->rev[i]) hipEventDestroy(c->rev[i]);
   delete c;
 }
 
 size_t pc_hac_workspace_bytes(int64_t n, int32_t d, int32_t linkage, const pc_options *opt) {
   if (n < 1 || d < 1 || d > kMaxDim || n > 2147483646LL || linkage < 0 || linkage > 3) return 0;
+  if (opt && (opt->precision < 0 || opt->precision > 2)) return 0;
   State S;
-  size_t bytes = layout(S, nullptr, n, d, linkage, true);
+  size_t bytes = layout(S, nullptr, n, d, linkage, true, opt ? opt->precision : 0);
   const bool gram = d >= kGramMinDim && d <= kGramMaxDim;
   // initial candidate record (grown on demand), pair list, tiles and filter
   const size_t cand = (size_t)std::max<int64_t>(1 << 22, 4 * n);
@@ -288,18 +318,23 @@ constexpr long long kMaxRecord = 1LL << 30;
 // Scan partials: one per 1024 elements of the longest scan of the call.
 static pc_status grow_part(pc_context *ctx, State &S, long long longest_scan) {
   const long long need = longest_scan / 1024 + 1024;
-  HIPCHK(grow(ctx->part, (size_t)need * sizeof(long long)));
+  HIPCHK(grow(ctx, ctx->part, (size_t)need * sizeof(long long)));
   S.part = (long long *)ctx->part.p;
   S.part_cap = (long long)(ctx->part.bytes / sizeof(long long));
   return PC_OK;
 }
 
+// per pair: tile prefix (i64), chunk prefix (i64), value (f64), pending
+// value (f64), t, c, kR, kS, pending t, pending c (i32)
+constexpr size_t kPairBytes = 4 * sizeof(long long) + 6 * sizeof(int);
+// per candidate: lower bound, value, screening bound (f64), tile prefix
+// (i64), point ranges (int4), terminal, cluster, small-list entry (i32)
+constexpr size_t kCandBytes = 3 * sizeof(double) + sizeof(long long) + sizeof(int4) + 4 * sizeof(int);
+
 static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
   if (cap > kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round needs more than 2^30 cluster pairs");
-  // per pair: tile prefix (i64), chunk prefix (i64), value (f64), pending
-  // value (f64), t, c, kR, kS, pending t, pending c (i32)
-  const size_t per = 4 * sizeof(long long) + 6 * sizeof(int);
-  HIPCHK(grow(ctx->pairs, (size_t)cap * per + 1024));
+  const size_t per = kPairBytes;
+  HIPCHK(grow(ctx, ctx->pairs, (size_t)cap * per + 1024));
   char *b = (char *)ctx->pairs.p;
   const long long pc = (long long)((ctx->pairs.bytes - 1024) / per);
   S.pair_cap = pc;
@@ -318,14 +353,14 @@ static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
 
 static pc_status grow_fidx(pc_context *ctx, State &S, long long cap) {
   if (cap > 8 * kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round's pair filter needs too many points");
-  HIPCHK(grow(ctx->fidx, (size_t)cap * sizeof(int)));
+  HIPCHK(grow(ctx, ctx->fidx, (size_t)cap * sizeof(int)));
   S.fidx = (int *)ctx->fidx.p;
   S.fidx_cap = (long long)(ctx->fidx.bytes / sizeof(int));
   return PC_OK;
 }
 
 static pc_status grow_tiles(pc_context *ctx, State &S, long long cap) {
-  HIPCHK(grow(ctx->tiles, (size_t)cap * sizeof(double)));
+  HIPCHK(grow(ctx, ctx->tiles, (size_t)cap * sizeof(double)));
   S.tile_v = (double *)ctx->tiles.p;
   S.tile_cap = (long long)(ctx->tiles.bytes / sizeof(double));
   return PC_OK;
@@ -333,10 +368,8 @@ static pc_status grow_tiles(pc_context *ctx, State &S, long long cap) {
 
 static pc_status grow_cand(pc_context *ctx, State &S, long long cap) {
   if (cap > kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round needs more than 2^30 recorded candidates");
-  // per candidate: lower bound, value, screening bound (f64), tile prefix
-  // (i64), point ranges (int4), terminal, cluster, small-list entry (i32)
-  const size_t per = 3 * sizeof(double) + sizeof(long long) + sizeof(int4) + 4 * sizeof(int);
-  HIPCHK(grow(ctx->cand, (size_t)cap * per + 1024));
+  const size_t per = kCandBytes;
+  HIPCHK(grow(ctx, ctx->cand, (size_t)cap * per + 1024));
   const long long cc = (long long)((ctx->cand.bytes - 1024) / per);
   S.cand_cap = cc;
   S.cd_lb = (double *)ctx->cand.p;
@@ -367,7 +400,8 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   int cache_slots = opt ? opt->cache_slots : -1;
   if (cache_slots < 0) cache_slots = linkage == kAverage ? 64 : 0;
   if (centroid_link(linkage)) cache_slots = 0;  // Ward / avg-2 values cost less than a probe
-  if (opt && opt->precision != PC_PREC_EXACT) return fail(PC_ERR_UNSUPPORTED, "precision mode not available");
+  const int elem = opt ? opt->precision : PC_PREC_FP16_REFINE;
+  if (elem < PC_PREC_FP16_REFINE || elem > PC_PREC_FP32) return fail(PC_ERR_INVALID_ARG, "unknown precision");
   if (!points_on_device) {
     for (int64_t i = 0; i < n * (int64_t)d; ++i)
       if (!std::isfinite(points[i])) return fail(PC_ERR_NONFINITE_INPUT, "non-finite coordinate");
@@ -391,13 +425,14 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     return PC_OK;
   }
 
+  ctx->over_budget = false;
   State S;
   memset(&S, 0, sizeof(S));
-  const size_t need = layout(S, nullptr, n, d, linkage, !points_on_device);
-  HIPCHK(grow(ctx->ws, need));
+  const size_t need = layout(S, nullptr, n, d, linkage, !points_on_device, elem);
+  HIPCHK(grow(ctx, ctx->ws, need));
   float *xstage = nullptr;
   pc_merge *rstage = nullptr;
-  layout(S, (char *)ctx->ws.p, n, d, linkage, !points_on_device, &xstage, &rstage);
+  layout(S, (char *)ctx->ws.p, n, d, linkage, !points_on_device, elem, &xstage, &rstage);
   S.n = (int)n;
   S.d = d;
   S.linkage = linkage;
@@ -422,6 +457,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   S.tree = tree_ok ? 1 : 0;
   S.gram = (!tree_ok && gram_ok) ? 1 : 0;
   S.tev = ctx->tev;
+  S.rev = ctx->rev;
   S.xin = nullptr;  // set once the device copy of the points is known
   double kms[4] = {0, 0, 0, 0};
   long long klaunch[4] = {0, 0, 0, 0};
@@ -480,7 +516,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
       while (c2 < want) c2 <<= 1;
       if (c2 < cap) cap = c2;
     }
-    for (int i = 0; i < 2; ++i) HIPCHK(grow(ctx->cache[i], (size_t)cap * 2 * sizeof(unsigned long long)));
+    for (int i = 0; i < 2; ++i) HIPCHK(grow(ctx, ctx->cache[i], (size_t)cap * 2 * sizeof(unsigned long long)));
     S.cache_mask = cap - 1;
     S.ck = (unsigned long long *)ctx->cache[0].p;
     S.cv = S.ck + cap;
@@ -510,10 +546,12 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   if (const char *e = getenv("PC_TEST_GRAM_BATCH")) gram_batch = std::max<long long>(1, atoll(e));
   int nact = (int)n;
   int merges = 0;
-  long long rounds = 0, terms = 0, ovfq = 0;
+  long long rounds = 0, terms = 0, ovfq = 0, gram_terms = 0;
+  double ms_nn = 0.0, ms_merge = 0.0, ms_update = 0.0;
   Counters &h = *ctx->hcnt;
   while (nact > 1) {
     if (rounds > n) return fail(PC_ERR_DEVICE, "round loop did not converge");
+    if (S.timing) HIPCHK(hipEventRecord(ctx->rev[0], s));
     if (tree_ok) {
       const bool use_tree = !gram_ok || tree_gram_switch <= 0 || nact > tree_gram_switch;
       S.tree = use_tree ? 1 : 0;
@@ -595,9 +633,10 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
           S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;
           launch_cache_unclaim(S, s);
           bool shrink = false;
+          // (beyond the record limit or the context's budget: fewer terminals)
           if (h.cand_overflow) {
             const long long want = h.n_cand + h.n_cand / 2 + 1024;
-            if (want <= kMaxRecord) {
+            if (want <= kMaxRecord && fits(ctx, ctx->cand, (size_t)want * kCandBytes + 1024)) {
               pc_status st = grow_cand(ctx, S, want);
               if (st != PC_OK) return st;
             } else {
@@ -606,7 +645,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
           }
           if (pover) {
             const long long want = std::max<long long>(h.n_pairs, h.n_pend) * 3 / 2 + 1024;
-            if (want <= kMaxRecord) {
+            if (want <= kMaxRecord && fits(ctx, ctx->pairs, (size_t)want * kPairBytes + 1024)) {
               pc_status st = grow_pairs(ctx, S, want);
               if (st != PC_OK) return st;
             } else {
@@ -676,10 +715,19 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
       if (st != PC_OK) return st;
       if (too_big) return fail(PC_ERR_OUT_OF_MEMORY, "a round's pair evaluation exceeds the record limits");
     }
-    launch_round_tail(S, (int)rounds, nact, merges, s);
+    if (S.gram) gram_terms += h.n_term;
+    if (S.timing) HIPCHK(hipEventRecord(ctx->rev[1], s));
+    launch_round_tail(S, (int)rounds, nact, merges, s);  // records rev[2] after the merges when timing
     HIPCHK(hipGetLastError());
+    if (S.timing) HIPCHK(hipEventRecord(ctx->rev[3], s));
     HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (S.timing) {
+      float a = 0.f, b = 0.f, c = 0.f;
+      if (hipEventElapsedTime(&a, ctx->rev[0], ctx->rev[1]) == hipSuccess) ms_nn += a;
+      if (hipEventElapsedTime(&b, ctx->rev[1], ctx->rev[2]) == hipSuccess) ms_merge += b;
+      if (hipEventElapsedTime(&c, ctx->rev[2], ctx->rev[3]) == hipSuccess) ms_update += c;
+    }
     if (h.nonfinite == 2) return fail(PC_ERR_DEVICE, "a terminal found no neighbour");
     if (h.nonfinite == 3) return fail(PC_ERR_DEVICE, "internal index check failed");
     if (h.nonfinite == 4) return fail(PC_ERR_DEVICE, "a claimed cache entry was never filled");
@@ -743,6 +791,11 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     stats->cache_inserts = h.cache_inserts;
     stats->cache_fail = h.cache_fail;
     stats->cache_derived = h.cache_derived;
+    stats->refined = h.refined;
+    stats->fp64_fallbacks = h.refined > gram_terms ? h.refined - gram_terms : 0;
+    stats->ms_nn = ms_nn;
+    stats->ms_merge = ms_merge;
+    stats->ms_update = ms_update;
   }
   g_err.clear();
   return PC_OK;

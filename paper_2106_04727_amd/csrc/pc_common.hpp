@@ -36,6 +36,10 @@ inline int gram_kp(int d) {
 }
 constexpr uint32_t kInfBits = 0x7f800000u;
 
+// element type of the MFMA screening tiles (pc_options.precision)
+enum ScreenElem { kElF16 = 0, kElBF16 = 1, kElF32 = 2 };
+inline int screen_elem_bytes(int e) { return e == kElF32 ? 4 : 2; }
+
 // avg-1 is the mean Euclidean distance, avg-2 the mean squared distance
 enum Linkage { kComplete = 0, kAverage = 1, kWard = 2, kAvgSq = 3 };
 
@@ -121,6 +125,7 @@ struct Counters {
   long long n_small;   // small candidates of the current batch
   long long n_scr;     // screened candidates of the current batch
   int n_scr32, pad_scr;
+  long long refined;   // screened candidates given an exact FP64 value
 };
 
 // All device arrays of one clustering call. Slots are storage indices of
@@ -207,12 +212,13 @@ struct State {
   // recentred on gorg and scaled by gscale, with FP64 norms of the rounded values
   int gram;             // 1: this call searches with MFMA Gram tiles
   int gkp;              // padded K (multiple of 16)
-  _Float16 *g16;        // n x gkp, in active-list order
+  int elem;             // ScreenElem: FP16 / BF16 / FP32 operands of the screening tiles
+  _Float16 *g16;        // n x gkp elements of that type, in active-list order
   float4 *gq;  // per active item: pass-0 norm term, rigorous norm, rounding error, size/spread term
   // interval screening (complete/average): FP16 points in their current
   // places and their terms (|x~|^2, e, eta), the fixed point scaling, and the
   // candidates' tile prefix
-  _Float16 *p16;
+  _Float16 *p16;        // n x gkp elements of the screening type
   float4 *pq;
   double *porg, *pscale;
   long long *cd_tile0;
@@ -245,6 +251,7 @@ struct State {
   // optional kernel timing: event pairs around ring search, full scan, tiles
   int timing;
   hipEvent_t *tev;      // 8 events (start/end per kernel), owned by the context
+  hipEvent_t *rev;      // 4 events per round (start, search done, merge done, end)
   int tlaunched[4];     // kernels launched since the last read (host side)
 };
 

@@ -2262,7 +2262,48 @@ __global__ void k_pending_key(State S) {
 //     D^2 + spreads (mean squared point distance <= largest), average D
 //     (centroid distance <= mean distance, Sec. 4.2).
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float float16v __attribute__((ext_vector_type(16)));
+
+// Element type of the screening tiles (pc_options.precision): FP16 or BF16
+// operands on the 32x32x16 MFMA, or FP32 operands on the 32x32x2 MFMA; FP32
+// accumulation in every case. The rounding error of each rounded vector is
+// measured from its actual rounded values (eta below), so every bound holds
+// for any of them; FP32 products are not exact, which the accumulation
+// allowance covers (kElAllow).
+template <int E> struct El;
+template <> struct El<kElF16> {
+  typedef _Float16 T;
+  static constexpr int KS = 16;  // K of one MFMA
+  __device__ static T from(float f) { return (T)f; }
+  __device__ static float to(T v) { return (float)v; }
+  __device__ static float16v mma(const T *a, const T *b, float16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(*(const half8 *)a, *(const half8 *)b, c, 0, 0, 0);
+  }
+};
+template <> struct El<kElBF16> {
+  typedef __bf16 T;
+  static constexpr int KS = 16;
+  __device__ static T from(float f) { return (T)f; }
+  __device__ static float to(T v) { return (float)v; }
+  __device__ static float16v mma(const T *a, const T *b, float16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8 *)a, *(const bf16x8 *)b, c, 0, 0, 0);
+  }
+};
+template <> struct El<kElF32> {
+  typedef float T;
+  static constexpr int KS = 2;
+  __device__ static T from(float f) { return f; }
+  __device__ static float to(T v) { return v; }
+  __device__ static float16v mma(const T *a, const T *b, float16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(*a, *b, c, 0, 0, 0);
+  }
+};
+// elements per 16-byte chunk; LDS rows are padded by one chunk
+template <int E> constexpr int el_chunk() { return 16 / (int)sizeof(typename El<E>::T); }
+// the FP32 accumulation allowance per vector, in units of 2^-24 |x~|^2 per
+// term: products of 16-bit operands are exact in FP32, FP32 products round
+__host__ __device__ constexpr double kElAllow(int e) { return e == kElF32 ? 3.0 : 2.0; }
 constexpr int kGT = 64;                      // block tile: 64 terminals x 64 candidates
 constexpr float kGMargin = 1.0f + 1.0f / 16384.0f;  // outward margin of the FP32 tests
 
@@ -2335,7 +2376,10 @@ __global__ void k_gram_reset(State S) {
 // the bound pass estimate), y = |x~|^2 - e rounded down, z = eta rounded up,
 // w = 1/size (Ward) or the mean squared spread rounded down (complete, avg-2).
 // A wave per item, lanes over dims.
+template <int E>
 __global__ void k_gram_prep(State S) {
+  typedef typename El<E>::T T;
+  T *g = reinterpret_cast<T *>(S.g16);
   const int nact = S.cnt->n_act, d = S.d, kp = S.gkp;
   const double sc = *S.gscale;
   const int lane = threadIdx.x & (kWave - 1);
@@ -2345,22 +2389,23 @@ __global__ void k_gram_prep(State S) {
     const double *c = S.wcen + (size_t)sl * d;
     double nrm = 0.0, err = 0.0;
     for (int k = lane; k < kp; k += kWave) {
-      _Float16 h = (_Float16)0.0f;
+      T h = El<E>::from(0.0f);
       if (k < d) {
         const double xs = (c[k] - S.gorg[k]) * sc;
-        h = (_Float16)(float)xs;
-        const double hv = (double)(float)h;
+        h = El<E>::from((float)xs);
+        const double hv = (double)El<E>::to(h);
         nrm += hv * hv;
         err += (xs - hv) * (xs - hv);
       }
-      S.g16[(size_t)i * kp + k] = h;
+      g[(size_t)i * kp + k] = h;
     }
     nrm = wave_sum(nrm);
     err = wave_sum(err);
     if (lane == 0) {
-      // FP32 accumulation of kp exact products, plus the FP32 roundings of
-      // the norms and of |x~|^2 + |y~|^2 - 2 x~.y~, with a factor 2 to spare
-      const double e = 2.0 * (double)(kp + 8) * 5.9604644775390625e-8 * nrm + 1e-30;
+      // FP32 accumulation of kp exact products (FP32 operands: rounded
+      // products too), plus the FP32 roundings of the norms and of
+      // |x~|^2 + |y~|^2 - 2 x~.y~, with a factor 2 to spare
+      const double e = kElAllow(E) * (double)(kp + 8) * 5.9604644775390625e-8 * nrm + 1e-30;
       // eta: the rounding error, plus the FP64 error of the scaled centroid
       const double eta = sqrt(err) * (1.0 + 1e-12) + 1e-15 * sqrt(nrm) + 1e-18;
       double v = 0.0;
@@ -2429,33 +2474,41 @@ __device__ double gram_pick_upper(const State &S, int t, int c) {
 // Stage a 64-row tile of FP16 vectors in LDS. Pass 0 augments them so that
 // the MFMA result is the bound pass estimate: rows get (x~, a, 1), columns
 // (-2 y~, 1, b), with a, b the norm terms, so the product is a + b - 2 x~.y~.
-template <int KP, int PASS, bool ROW>
-__device__ __forceinline__ void gram_stage(const State &S, _Float16 (*dst)[KP + 8], const int *src_idx,
-                                           const float *aug, int nvalid, int d) {
-  constexpr int CH = KP / 8;  // 16-byte chunks per row
+template <int KP, int PASS, bool ROW, int E>
+__device__ __forceinline__ void gram_stage(const State &S, typename El<E>::T (*dst)[KP + el_chunk<E>()],
+                                           const int *src_idx, const float *aug, int nvalid, int d) {
+  typedef typename El<E>::T T;
+  constexpr int EPC = el_chunk<E>();  // elements per 16-byte chunk
+  constexpr int CH = KP / EPC;        // chunks per row
+  const T *g = reinterpret_cast<const T *>(S.g16);
   for (int j = threadIdx.x; j < kGT * CH; j += kBlock) {
     const int r = j / CH, c8 = j % CH;
-    half8 v = {};
+    uint4 raw = make_uint4(0, 0, 0, 0);
     if (r < nvalid) {
-      v = *(const half8 *)(S.g16 + (size_t)src_idx[r] * KP + c8 * 8);
+      raw = *(const uint4 *)(g + (size_t)src_idx[r] * KP + c8 * EPC);
       if (PASS == 0) {
+        T v[EPC];
+        __builtin_memcpy(v, &raw, 16);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = c8 * 8 + e;
-          if (!ROW && k < d) v[e] = v[e] * (_Float16)(-2.0f);
-          if (k == d) v[e] = ROW ? (_Float16)aug[r] : (_Float16)1.0f;
-          if (k == d + 1) v[e] = ROW ? (_Float16)1.0f : (_Float16)aug[r];
+        for (int e = 0; e < EPC; ++e) {
+          const int k = c8 * EPC + e;
+          if (!ROW && k < d) v[e] = El<E>::from(El<E>::to(v[e]) * -2.0f);  // exact
+          if (k == d) v[e] = El<E>::from(ROW ? aug[r] : 1.0f);
+          if (k == d + 1) v[e] = El<E>::from(ROW ? 1.0f : aug[r]);
         }
+        __builtin_memcpy(&raw, v, 16);
       }
     }
-    *(half8 *)&dst[r][c8 * 8] = v;
+    *(uint4 *)&dst[r][c8 * EPC] = raw;
   }
 }
 
-template <int LINK, int KP, int PASS>
+template <int LINK, int KP, int PASS, int E>
 __global__ __launch_bounds__(kBlock) void k_gram(State S) {
-  __shared__ __attribute__((aligned(16))) _Float16 sq[kGT][KP + 8];
-  __shared__ __attribute__((aligned(16))) _Float16 sc[kGT][KP + 8];
+  typedef typename El<E>::T T;
+  constexpr int KS = El<E>::KS;
+  __shared__ __attribute__((aligned(16))) T sq[kGT][KP + el_chunk<E>()];
+  __shared__ __attribute__((aligned(16))) T sc[kGT][KP + el_chunk<E>()];
   __shared__ float4 qd[kGT], cd[kGT];
   __shared__ float qaug[kGT], caug[kGT], qthr[kGT];
   __shared__ int qs[kGT], qt[kGT], qp[kGT], cs[kGT], cidx[kGT];
@@ -2501,7 +2554,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
     }
   }
   __syncthreads();
-  gram_stage<KP, PASS, true>(S, sq, cidx, qaug, nq, d);
+  gram_stage<KP, PASS, true, E>(S, sq, cidx, qaug, nq, d);
   // this lane's 16 rows (MFMA 32x32 output layout)
   float rq[16], rz[16], rt[16], re[16];
   int pmin = 0x7fffffff, pmax = -1;
@@ -2546,16 +2599,15 @@ __global__ __launch_bounds__(kBlock) void k_gram(State S) {
       }
     }
     __syncthreads();
-    gram_stage<KP, PASS, false>(S, sc, cidx, caug, nc, d);
+    gram_stage<KP, PASS, false, E>(S, sc, cidx, caug, nc, d);
     __syncthreads();
     if (threadIdx.x == 0) pairs += (long long)nq * nc;
     float16v acc = {};
+    // lanes 0-31 hold k values [kk, kk + KS/2) of their row, lanes 32-63 the rest
 #pragma unroll
-    for (int kk = 0; kk < KP; kk += 16) {
-      const half8 a = *(const half8 *)&sq[wr + (lane & 31)][kk + (lane >> 5) * 8];
-      const half8 b = *(const half8 *)&sc[wc + (lane & 31)][kk + (lane >> 5) * 8];
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
-    }
+    for (int kk = 0; kk < KP; kk += KS)
+      acc = El<E>::mma(&sq[wr + (lane & 31)][kk + (lane >> 5) * (KS / 2)],
+                       &sc[wc + (lane & 31)][kk + (lane >> 5) * (KS / 2)], acc);
     const int col = wc + (lane & 31);
     const int ci = c0 + col;
     const float4 cg = cd[col];
@@ -2727,7 +2779,10 @@ __global__ void k_pt_setup(State S) {
 
 // FP16 copy of every point in its current (permuted) place, and its FP32
 // terms: x = |x~|^2, y = e, z = eta (rounded up). A wave per point.
+template <int E>
 __global__ void k_pt_prep(State S) {
+  typedef typename El<E>::T T;
+  T *g = reinterpret_cast<T *>(S.p16);
   const int n = S.n, d = S.d, kp = S.gkp;
   const double sc = *S.pscale;
   const int lane = threadIdx.x & (kWave - 1);
@@ -2736,20 +2791,20 @@ __global__ void k_pt_prep(State S) {
     const float *p = S.px + (size_t)i * d;
     double nrm = 0.0, err = 0.0;
     for (int k = lane; k < kp; k += kWave) {
-      _Float16 h = (_Float16)0.0f;
+      T h = El<E>::from(0.0f);
       if (k < d) {
         const double xs = ((double)p[k] - S.porg[k]) * sc;
-        h = (_Float16)(float)xs;
-        const double hv = (double)(float)h;
+        h = El<E>::from((float)xs);
+        const double hv = (double)El<E>::to(h);
         nrm += hv * hv;
         err += (xs - hv) * (xs - hv);
       }
-      S.p16[(size_t)i * kp + k] = h;
+      g[(size_t)i * kp + k] = h;
     }
     nrm = wave_sum(nrm);
     err = wave_sum(err);
     if (lane == 0) {
-      const double e = 2.0 * (double)(kp + 8) * 5.9604644775390625e-8 * nrm + 1e-30;
+      const double e = kElAllow(E) * (double)(kp + 8) * 5.9604644775390625e-8 * nrm + 1e-30;
       const double eta = sqrt(err) * (1.0 + 1e-12) + 1e-15 * sqrt(nrm) + 1e-18;
       S.pq[i] = make_float4((float)nrm, f32_up(e), f32_up(eta * (double)kGMargin), 0.0f);
     }
@@ -2966,11 +3021,15 @@ __global__ void k_cand_small(State S) {
 // contributions are added (average) or maxed (complete) into the candidate.
 // Each block walks a contiguous range of tiles; the next tile's points are
 // loaded into registers while the current one is computed.
-template <int LINK, int KP>
+template <int LINK, int KP, int EL>
 __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
-  constexpr int CH = KP / 8;                           // 16-byte chunks per point
+  typedef typename El<EL>::T T;
+  constexpr int KS = El<EL>::KS;
+  constexpr int EPC = el_chunk<EL>();                   // elements per 16-byte chunk
+  constexpr int CH = KP / EPC;                         // 16-byte chunks per point
   constexpr int NCH = (2 * kGT * CH + kBlock - 1) / kBlock;  // chunks per thread (both sides)
-  __shared__ __attribute__((aligned(16))) _Float16 sab[2][kGT][KP + 8];
+  __shared__ __attribute__((aligned(16))) T sab[2][kGT][KP + EPC];
+  const T *pts = reinterpret_cast<const T *>(S.p16);
   __shared__ float an[2][kGT];
   __shared__ float side[2][3];  // per side: sum eta, max eta, max e
   __shared__ float red[3][kBlock / kWave];
@@ -3040,7 +3099,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
       uint4 v = make_uint4(0, 0, 0, 0);
       if (j < 2 * kGT * CH) {
         const int sd = j / (kGT * CH), r = (j / CH) % kGT, c8 = j % CH;
-        if (r < (sd ? nc : nr)) v = *(const uint4 *)(S.p16 + (size_t)((sd ? bb : ba) + r) * KP + c8 * 8);
+        if (r < (sd ? nc : nr)) v = *(const uint4 *)(pts + (size_t)((sd ? bb : ba) + r) * KP + c8 * EPC);
       }
       reg[u] = v;
     }
@@ -3105,7 +3164,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
       const int j = threadIdx.x + u * kBlock;
       if (j < 2 * kGT * CH) {
         const int sd = j / (kGT * CH), r = (j / CH) % kGT, c8 = j % CH;
-        *(uint4 *)&sab[sd][r][c8 * 8] = reg[u];
+        *(uint4 *)&sab[sd][r][c8 * EPC] = reg[u];
       }
     }
     if (prune && threadIdx.x == 0) {
@@ -3131,11 +3190,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
     const long long nxt = next_tile(tile + 1);  // its points in flight during the tile's arithmetic
     float16v acc = {};
 #pragma unroll
-    for (int kk = 0; kk < KP; kk += 16) {
-      const half8 a = *(const half8 *)&sab[0][wr + (lane & 31)][kk + (lane >> 5) * 8];
-      const half8 b = *(const half8 *)&sab[1][wc + (lane & 31)][kk + (lane >> 5) * 8];
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
-    }
+    for (int kk = 0; kk < KP; kk += KS)
+      acc = El<EL>::mma(&sab[0][wr + (lane & 31)][kk + (lane >> 5) * (KS / 2)],
+                       &sab[1][wc + (lane & 31)][kk + (lane >> 5) * (KS / 2)], acc);
     const int col = wc + (lane & 31);
     const bool cval = col < ncl;
     const float cn = an[1][col];
@@ -3247,17 +3304,19 @@ template <int LINK>
 __global__ void k_gram_exact(State S) {
   if (S.cnt->cand_overflow) return;  // the round is redone with a larger record
   const int nc = (int)min(S.cnt->n_cand, S.cand_cap), d = S.d;
-  long long evals = 0, ppairs = 0, hits = 0;
+  long long evals = 0, ppairs = 0, hits = 0, refined = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
     const int ti = S.cd_t[i], c = S.cd_c[i];
     const double lb = S.cd_lb[i];
     if (!centroid_link(LINK) && lb < 0.0) {
       // exact value of a small pair, from the triage pass
       atomicMin(&S.t_min[ti], pos_bits(S.cd_v[i]));
+      ++refined;
       continue;
     }
     S.cd_v[i] = NAN;
     if (lb > S.t_beta[ti] * kSlack) continue;
+    ++refined;
     const int t = S.term[ti];
     double v;
     if (centroid_link(LINK)) {
@@ -3309,6 +3368,7 @@ __global__ void k_gram_exact(State S) {
   count_add(&S.cnt->cluster_evals, evals);
   count_add(&S.cnt->point_pairs, ppairs);
   count_add(&S.cnt->cache_hits, hits);
+  count_add(&S.cnt->refined, refined);
 }
 
 // After every value of the round is in t_min: the lowest cluster ID among the
@@ -3575,7 +3635,7 @@ inline int nblk(long long n, int cap = 4096) {
 
 inline void tmark(State &S, int k, bool end, hipStream_t s) {
   if (!S.timing) return;
-  hipEventRecord(S.tev[2 * k + (end ? 1 : 0)], s);
+  (void)hipEventRecord(S.tev[2 * k + (end ? 1 : 0)], s);
   if (end) S.tlaunched[k] = 1;
 }
 
@@ -3644,24 +3704,37 @@ void launch_emit(State &S, int nact, hipStream_t s, int *t_ovf) {
   }
 }
 
-template <int LINK, int KP>
-void launch_gram_kp(State &S, int nact, hipStream_t s) {
+template <int LINK, int KP, int E>
+void launch_gram_kpe(State &S, int nact, hipStream_t s) {
   const int nb = S.tb1 - S.tb0;
   const int gx = (nb + kGT - 1) / kGT;
   int gy = 4096 / (gx > 0 ? gx : 1);
   const int maxy = (nact + kGT - 1) / kGT;
   gy = gy < 1 ? 1 : (gy > maxy ? maxy : gy);
   tmark(S, 0, false, s);
-  k_gram<LINK, KP, 0><<<dim3(gx, gy), kBlock, 0, s>>>(S);
+  k_gram<LINK, KP, 0, E><<<dim3(gx, gy), kBlock, 0, s>>>(S);
   tmark(S, 0, true, s);
   tmark(S, 3, false, s);
-  k_gram<LINK, KP, 1><<<dim3(gx, gy), kBlock, 0, s>>>(S);
+  k_gram<LINK, KP, 1, E><<<dim3(gx, gy), kBlock, 0, s>>>(S);
   tmark(S, 3, true, s);
 }
 
 template <int LINK, int KP>
+void launch_gram_kp(State &S, int nact, hipStream_t s) {
+  switch (S.elem) {
+  case kElBF16: launch_gram_kpe<LINK, KP, kElBF16>(S, nact, s); break;
+  case kElF32: launch_gram_kpe<LINK, KP, kElF32>(S, nact, s); break;
+  default: launch_gram_kpe<LINK, KP, kElF16>(S, nact, s); break;
+  }
+}
+
+template <int LINK, int KP>
 void launch_cand_tiles(State &S, int ncand, hipStream_t s) {
-  k_cand_tiles<LINK, KP><<<8192, kBlock, 0, s>>>(S, ncand);
+  switch (S.elem) {
+  case kElBF16: k_cand_tiles<LINK, KP, kElBF16><<<8192, kBlock, 0, s>>>(S, ncand); break;
+  case kElF32: k_cand_tiles<LINK, KP, kElF32><<<8192, kBlock, 0, s>>>(S, ncand); break;
+  default: k_cand_tiles<LINK, KP, kElF16><<<8192, kBlock, 0, s>>>(S, ncand); break;
+  }
 }
 
 // Candidates of a batch: interval screening (complete/average), then exact
@@ -3698,8 +3771,21 @@ void launch_gram_setup(State &S, int nact, hipStream_t s) {
   k_gram_reset<<<1, kGramMaxDim, 0, s>>>(S);
   k_gram_range<<<nblk((long long)nact * kWave, 1024), kBlock, 0, s>>>(S);
   k_gram_setup<<<1, kGramMaxDim, 0, s>>>(S);
-  k_gram_prep<<<nblk((long long)nact * kWave, 4096), kBlock, 0, s>>>(S);
-  if (S.p16) k_pt_prep<<<nblk((long long)S.n * kWave, 4096), kBlock, 0, s>>>(S);
+  const int gp = nblk((long long)nact * kWave, 4096), pp = nblk((long long)S.n * kWave, 4096);
+  switch (S.elem) {
+  case kElBF16:
+    k_gram_prep<kElBF16><<<gp, kBlock, 0, s>>>(S);
+    if (S.p16) k_pt_prep<kElBF16><<<pp, kBlock, 0, s>>>(S);
+    break;
+  case kElF32:
+    k_gram_prep<kElF32><<<gp, kBlock, 0, s>>>(S);
+    if (S.p16) k_pt_prep<kElF32><<<pp, kBlock, 0, s>>>(S);
+    break;
+  default:
+    k_gram_prep<kElF16><<<gp, kBlock, 0, s>>>(S);
+    if (S.p16) k_pt_prep<kElF16><<<pp, kBlock, 0, s>>>(S);
+    break;
+  }
   if (S.p16 && S.linkage == kComplete && S.d <= kBlkMaxDim)
     k_blk_boxes<<<nblk((S.n + 63) / 64, 4096), kBlock, 0, s>>>(S);
 }
@@ -3918,6 +4004,7 @@ void launch_round_tail(State &S, int round, int nact, int merges_before, hipStre
   k_merge<<<nblk(nact / 2 + 1, 2048), kBlock, 0, s>>>(S, merges_before);
   if (S.linkage == kComplete && S.d == 2)
     k_merge_sup<<<nblk((long long)(nact / 2 + 1) * kSupDirs, 8192), kBlock, 0, s>>>(S);
+  if (S.timing) (void)hipEventRecord(S.rev[2], s);
   k_alive_flags<<<gb, kBlock, 0, s>>>(S);
   int *total = S.scan + S.n;  // one spare int past the scan array
   scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, total, S.part, s);

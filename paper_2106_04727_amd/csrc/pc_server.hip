@@ -3,14 +3,21 @@
 //
 // A server owns `slots` workers. Each worker has its own context (device
 // workspace) and HIP stream, so the rounds of the requests it runs overlap on
-// the GPU with those of the other workers. A waiting request is admitted when
-// a worker is free and its device footprint (the workspace model of
-// pc_hac_workspace_bytes) fits into what is left of the HBM budget; requests
+// the GPU with those of the other workers. Device bytes are accounted per
+// slot: an idle slot counts what its context keeps from earlier requests, a
+// busy slot its request's reservation (at least that). A waiting request is
+// admitted when a worker is free and the reservation it adds (its footprint,
+// initially the workspace model of pc_hac_workspace_bytes, less what the
+// slot already holds) fits into what is left of the HBM budget; requests
 // are taken in arrival order, a later one that fits may start before an
 // earlier one that does not (first fit), and a request passed over kMaxBypass
-// times stops any further overtaking until it starts. The computation of a
-// request is pc_hac's, on the same inputs, so its rows do not depend on what
-// else runs.
+// times stops any further overtaking until it starts. While a request runs,
+// its slot's context may not hold more than the reservation; a request that
+// needs more (its candidate records grow with the data) stops, goes back to
+// the head of the queue with twice the reservation, and runs again when that
+// fits (it fails with PC_ERR_OUT_OF_MEMORY once the reservation would exceed
+// the whole budget). The computation of a request is pc_hac's, on the same
+// inputs, so its rows do not depend on what else runs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +36,8 @@
 namespace pc {
 size_t context_bytes(const pc_context *c);
 void context_trim(pc_context *c);
+void context_set_budget(pc_context *c, size_t bytes);
+bool context_over_budget(const pc_context *c);
 void set_error(const char *msg);  // the text pc_last_error() returns on this thread
 }  // namespace pc
 
@@ -46,7 +55,9 @@ struct Job {
   pc_options opt{};
   bool has_opt = false;
   pc_merge *out = nullptr;
-  uint64_t bytes = 0;
+  uint64_t model = 0;  // pc_hac_workspace_bytes of the request
+  uint64_t bytes = 0;  // its reservation (the model, doubled at each requeue)
+  int requeues = 0;
   int state = kQueued;
   int slot = -1;
   int bypassed = 0;
@@ -68,6 +79,7 @@ struct pc_server {
   int slots = 4;
   uint64_t budget = 0;
   double fake_us = 0.0;
+  double fake_growth = 1.0;  // test mode: a request's device need is model x this
   std::chrono::steady_clock::time_point t0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -78,19 +90,28 @@ struct pc_server {
   std::vector<pc_context *> ctxs;
   std::vector<hipStream_t> streams;
   bool stop = false;
+  // in_use = sum over slots of max(held, reserved)
+  std::vector<uint64_t> held;      // per slot: bytes its context keeps between requests
+  std::vector<uint64_t> reserved;  // per slot: the running request's reservation (0 if idle)
   uint64_t in_use = 0, peak_bytes = 0;
   int running = 0, peak_running = 0;
-  int64_t submitted = 0, completed = 0, rejected = 0, cancelled = 0, failed = 0;
+  int64_t submitted = 0, completed = 0, rejected = 0, cancelled = 0, failed = 0, requeued = 0;
 
   double now_ms() const {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
 
-  // first waiting request that fits, honouring the overtaking limit; caller holds mu
-  Job *pick() {
+  // bytes a request adds when it starts on `slot`
+  uint64_t extra(const Job *j, int slot) const {
+    return j->bytes > held[slot] ? j->bytes - held[slot] : 0;
+  }
+
+  // first waiting request that fits on `slot`, honouring the overtaking
+  // limit; caller holds mu
+  Job *pick(int slot) {
     for (size_t i = 0; i < queue.size(); ++i) {
       Job *j = queue[i];
-      if (j->bytes <= budget - in_use) {
+      if (extra(j, slot) <= budget - in_use) {
         for (size_t k = 0; k < i; ++k) ++queue[k]->bypassed;
         queue.erase(queue.begin() + (long)i);
         return j;
@@ -104,44 +125,86 @@ struct pc_server {
     if (fake_us <= 0.0) hipSetDevice(device);
     for (;;) {
       Job *j = nullptr;
+      uint64_t resv = 0;
       {
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
           if (stop) return;
-          j = pick();
+          j = pick(slot);
           if (j) break;
+          if (!queue.empty() && held[slot] > 0) {
+            // a waiting request does not fit: this idle slot gives back what
+            // its context keeps (the other idle slots do the same on waking)
+            in_use -= held[slot];
+            held[slot] = 0;
+            if (fake_us <= 0.0) pc::context_trim(ctxs[slot]);
+            cv_work.notify_all();
+            continue;
+          }
           cv_work.wait(lk);
         }
         j->state = kRunning;
         j->slot = slot;
-        j->t_start = now_ms();
-        in_use += j->bytes;
+        if (j->requeues == 0) j->t_start = now_ms();
+        resv = std::max(j->bytes, held[slot]);
+        in_use += resv - held[slot];
+        reserved[slot] = resv;
         peak_bytes = std::max(peak_bytes, in_use);
         ++running;
         peak_running = std::max(peak_running, running);
       }
       pc_status st = PC_OK;
+      bool over = false;
+      uint64_t keep = 0;
       if (fake_us > 0.0) {
-        // host-only test mode: occupy the slot for a time proportional to n
-        std::this_thread::sleep_for(std::chrono::duration<double, std::micro>(fake_us * (double)j->n / 1000.0));
-        for (int64_t r = 0; r + 1 < j->n; ++r) j->out[r] = pc_merge{0, 0, 0.0, 0};
+        // host-only test mode: occupy the slot for a time proportional to n;
+        // the request needs model x fake_growth bytes
+        const uint64_t need = (uint64_t)((double)j->model * fake_growth);
+        if (need > resv) {
+          over = true;
+          st = PC_ERR_OUT_OF_MEMORY;
+          keep = held[slot];
+        } else {
+          std::this_thread::sleep_for(std::chrono::duration<double, std::micro>(fake_us * (double)j->n / 1000.0));
+          for (int64_t r = 0; r + 1 < j->n; ++r) j->out[r] = pc_merge{0, 0, 0.0, 0};
+          keep = std::max(need, held[slot]);
+        }
       } else {
         j->stats.struct_size = sizeof(pc_stats);
+        pc::context_set_budget(ctxs[slot], resv);
         st = pc_hac(ctxs[slot], j->points, j->n, j->d, 0, j->linkage, j->has_opt ? &j->opt : nullptr, j->out, 0,
                     (void *)streams[slot], &j->stats);
+        over = st == PC_ERR_OUT_OF_MEMORY && pc::context_over_budget(ctxs[slot]);
         if (st != PC_OK) j->error = pc_last_error();
-        // keep the slot within its share of the budget
-        if (pc::context_bytes(ctxs[slot]) > budget / (uint64_t)slots) pc::context_trim(ctxs[slot]);
+        keep = pc::context_bytes(ctxs[slot]);
+      }
+      // keep the slot within its share of the budget
+      if (keep > budget / (uint64_t)slots) {
+        if (fake_us <= 0.0) pc::context_trim(ctxs[slot]);
+        keep = 0;
       }
       {
         std::lock_guard<std::mutex> lk(mu);
-        j->result = st;
-        j->state = kDone;
-        j->t_done = now_ms();
-        in_use -= j->bytes;
+        in_use = in_use - resv + keep;
+        held[slot] = keep;
+        reserved[slot] = 0;
         --running;
-        ++completed;
-        if (st != PC_OK) ++failed;
+        if (over && j->bytes < budget) {
+          // needs more than it reserved: back to the head of the queue
+          j->bytes = std::min<uint64_t>(2 * resv, budget);
+          ++j->requeues;
+          ++requeued;
+          j->state = kQueued;
+          j->slot = -1;
+          j->error.clear();
+          queue.push_front(j);
+        } else {
+          j->result = st;
+          j->state = kDone;
+          j->t_done = now_ms();
+          ++completed;
+          if (st != PC_OK) ++failed;
+        }
       }
       cv_done.notify_all();
       cv_work.notify_all();
@@ -165,7 +228,10 @@ pc_status pc_server_create(int device, const pc_server_options *opt, pc_server *
     return sfail(PC_ERR_INVALID_ARG, "at most 64 slots");
   }
   s->fake_us = opt ? opt->fake_us_per_kpoint : 0.0;
+  s->fake_growth = opt && opt->fake_growth > 0.0 ? opt->fake_growth : 1.0;
   s->budget = opt ? opt->hbm_budget_bytes : 0;
+  s->held.assign((size_t)s->slots, 0);
+  s->reserved.assign((size_t)s->slots, 0);
   if (s->fake_us > 0.0) {
     if (!s->budget) s->budget = 1ull << 30;
   } else {
@@ -189,7 +255,7 @@ pc_status pc_server_create(int device, const pc_server_options *opt, pc_server *
     }
     for (int i = 0; i < s->slots; ++i) {
       pc_context *c = nullptr;
-      pc_status st = pc_context_create(dev, &c);
+      pc_status st = pc_context_create(dev, 0, &c);
       hipStream_t hs = nullptr;
       if (st == PC_OK && hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess) st = PC_ERR_DEVICE;
       if (st != PC_OK) {
@@ -227,6 +293,7 @@ pc_status pc_server_submit(pc_server *s, const float *points, int64_t n, int32_t
     j->has_opt = true;
   }
   j->out = out;
+  j->model = bytes;
   j->bytes = bytes;
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -340,6 +407,7 @@ pc_status pc_server_get_stats(pc_server *s, pc_server_stats *st) {
   st->budget_bytes = s->budget;
   st->bytes_in_use = s->in_use;
   st->peak_bytes_in_use = s->peak_bytes;
+  if (st->struct_size >= sizeof(pc_server_stats)) st->requeued = s->requeued;
   return PC_OK;
 }
 

@@ -17,6 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libparchain.so")
 
 LINKAGES = {"complete": 0, "average": 1, "ward": 2, "avgsq": 3}
+# element type of the screening tiles (pc_precision)
+PRECISIONS = {"fp16": 0, "bf16": 1, "fp32": 2}
 
 PC_OK = 0
 STATUS = {
@@ -57,7 +59,9 @@ class pc_stats(ctypes.Structure):
                 ("ms_finalize", ctypes.c_double), ("kernel_ms", ctypes.c_double * 4),
                 ("kernel_launches", ctypes.c_int64 * 4), ("candidate_visits", ctypes.c_int64 * 4),
                 ("cache_hits", ctypes.c_int64), ("cache_inserts", ctypes.c_int64),
-                ("cache_fail", ctypes.c_int64), ("cache_derived", ctypes.c_int64)]
+                ("cache_fail", ctypes.c_int64), ("cache_derived", ctypes.c_int64),
+                ("refined", ctypes.c_int64), ("fp64_fallbacks", ctypes.c_int64),
+                ("ms_nn", ctypes.c_double), ("ms_merge", ctypes.c_double), ("ms_update", ctypes.c_double)]
 
     KERNELS = ("ring_search", "block_search", "pair_tiles", "ring_emit")
 
@@ -75,7 +79,8 @@ _lock = threading.Lock()
 
 class pc_server_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("slots", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_uint64), ("fake_us_per_kpoint", ctypes.c_double)]
+                ("hbm_budget_bytes", ctypes.c_uint64), ("fake_us_per_kpoint", ctypes.c_double),
+                ("fake_growth", ctypes.c_double)]
 
 
 class pc_request_info(ctypes.Structure):
@@ -101,7 +106,7 @@ class pc_server_stats(ctypes.Structure):
                 ("failed", ctypes.c_int64), ("running", ctypes.c_int32), ("queued", ctypes.c_int32),
                 ("peak_running", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("budget_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
-                ("peak_bytes_in_use", ctypes.c_uint64)]
+                ("peak_bytes_in_use", ctypes.c_uint64), ("requeued", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("struct_size", "reserved")}
@@ -124,7 +129,7 @@ def load_library(path: str | None = None):
             raise OSError("libparchain.so not built (%s); run __graft_entry__.build()" % p)
         lib = ctypes.CDLL(p)
         vp = ctypes.c_void_p
-        lib.pc_context_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+        lib.pc_context_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)]
         lib.pc_context_create.restype = ctypes.c_int
         lib.pc_context_destroy.argtypes = [vp]
         lib.pc_context_destroy.restype = None
@@ -172,17 +177,28 @@ def _link(linkage) -> int:
     return LINKAGES[linkage] if isinstance(linkage, str) else int(linkage)
 
 
-def workspace_bytes(n: int, d: int, linkage) -> int:
-    return int(load_library().pc_hac_workspace_bytes(n, d, _link(linkage), None))
+def _prec(precision) -> int:
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
+def _options(prune=True, timing=False, cache_slots=-1, precision="fp16") -> pc_options:
+    return pc_options(ctypes.sizeof(pc_options), _prec(precision), 1 if prune else 0, 1 if timing else 0,
+                      int(cache_slots), 0)
+
+
+def workspace_bytes(n: int, d: int, linkage, precision="fp16") -> int:
+    opt = _options(precision=precision)
+    return int(load_library().pc_hac_workspace_bytes(n, d, _link(linkage), ctypes.byref(opt)))
 
 
 class Context:
-    """A pc_context on one HIP device (owns the device workspace)."""
+    """A pc_context on one HIP device (owns the device workspace; at most
+    ``hbm_budget_bytes`` of it when that is > 0)."""
 
-    def __init__(self, device: int = -1):
+    def __init__(self, device: int = -1, hbm_budget_bytes: int = 0):
         self.lib = load_library()
         h = ctypes.c_void_p()
-        _check(self.lib, self.lib.pc_context_create(int(device), ctypes.byref(h)))
+        _check(self.lib, self.lib.pc_context_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
         self.handle = h
 
     def close(self):
@@ -198,10 +214,9 @@ class Context:
 
     def hac(self, points, n: int, d: int, linkage, out, *, points_on_device: bool,
             out_on_device: bool, stream=None, prune: bool = True, stats: bool = True,
-            timing: bool = False, cache_slots: int = -1):
+            timing: bool = False, cache_slots: int = -1, precision="fp16"):
         """Raw call: ``points``/``out`` are integer addresses."""
-        opt = pc_options(ctypes.sizeof(pc_options), 0, 1 if prune else 0, 1 if timing else 0,
-                         int(cache_slots), 0)
+        opt = _options(prune, timing, cache_slots, precision)
         st = pc_stats()
         st.struct_size = ctypes.sizeof(pc_stats)
         rc = self.lib.pc_hac(self.handle, ctypes.c_void_p(points), int(n), int(d),
@@ -223,7 +238,7 @@ def _ctx(device: int) -> Context:
 
 
 def hac_device(x, linkage, *, prune: bool = True, ctx: Context | None = None, stream=None,
-               timing: bool = False, cache_slots: int = -1):
+               timing: bool = False, cache_slots: int = -1, precision="fp16"):
     """Cluster a CUDA (HIP) float32 tensor of shape (n, d) that lives on the GPU.
 
     Returns ``(rows, stats)``: ``rows`` is an int64 device tensor (n-1, 4)
@@ -242,7 +257,7 @@ def hac_device(x, linkage, *, prune: bool = True, ctx: Context | None = None, st
         stream = torch.cuda.current_stream(x.device).cuda_stream
     st = ctx.hac(x.data_ptr(), n, d, linkage, rows.data_ptr(), points_on_device=True,
                  out_on_device=True, stream=stream, prune=prune, timing=timing,
-                 cache_slots=cache_slots)
+                 cache_slots=cache_slots, precision=precision)
     return rows[: n - 1], st
 
 
@@ -261,7 +276,7 @@ def rows_to_Z(rows) -> np.ndarray:
 
 
 def hac(x, linkage, *, prune: bool = True, device: int = 0, return_stats: bool = False,
-        cache_slots: int = -1):
+        cache_slots: int = -1, precision="fp16", timing: bool = False):
     """Cluster points (numpy array or tensor, (n, d) float32) on the GPU.
 
     Returns the scipy-convention linkage matrix Z (float64, (n-1, 4)).
@@ -272,7 +287,8 @@ def hac(x, linkage, *, prune: bool = True, device: int = 0, return_stats: bool =
         xt = x.to(torch.float32)
     else:
         xt = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).to("cuda:%d" % device)
-    rows, st = hac_device(xt, linkage, prune=prune, cache_slots=cache_slots)
+    rows, st = hac_device(xt, linkage, prune=prune, cache_slots=cache_slots, precision=precision,
+                          timing=timing)
     torch.cuda.synchronize(xt.device)
     Z = rows_to_Z(rows)
     return (Z, st) if return_stats else Z
@@ -286,20 +302,20 @@ class Server:
     """
 
     def __init__(self, device: int = 0, slots: int = 4, hbm_budget_bytes: int = 0,
-                 fake_us_per_kpoint: float = 0.0):
+                 fake_us_per_kpoint: float = 0.0, fake_growth: float = 1.0):
         self.lib = load_library()
         opt = pc_server_options(ctypes.sizeof(pc_server_options), int(slots), int(hbm_budget_bytes),
-                                float(fake_us_per_kpoint))
+                                float(fake_us_per_kpoint), float(fake_growth))
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.pc_server_create(int(device), ctypes.byref(opt), ctypes.byref(h)))
         self.handle = h
         self._keep = {}
 
-    def submit(self, x, linkage, *, cache_slots: int = -1, prune: bool = True) -> int:
+    def submit(self, x, linkage, *, cache_slots: int = -1, prune: bool = True, precision="fp16") -> int:
         x = np.ascontiguousarray(x, dtype=np.float32)
         n, d = x.shape
         out = np.zeros((max(n - 1, 1), 4), np.int64)
-        opt = pc_options(ctypes.sizeof(pc_options), 0, 1 if prune else 0, 0, int(cache_slots), 0)
+        opt = _options(prune, False, cache_slots, precision)
         t = ctypes.c_uint64()
         _check(self.lib, self.lib.pc_server_submit(self.handle, x.ctypes.data, n, d, _link(linkage),
                                                    ctypes.byref(opt), out.ctypes.data, ctypes.byref(t)))

@@ -90,7 +90,8 @@ def write(name: str) -> str:
         f.write("# Whole-tree digest of the FP64 oracle (accelerated mode), written by\n")
         f.write("# tests/golden/digests.py; see its docstring for the format.\n")
         f.write("name %s\ninput %s\nn %d\nd %d\nlinkage %s\n" % (name, expr, n, d, link))
-        f.write("min_gap %r\nzero_best %d\nqueries %d\n" % (cert["min_gap"], cert["zero_best"], cert["queries"]))
+        f.write("min_gap %r\nzero_best %d\nqueries %d\n" % (float(cert["min_gap"]), cert["zero_best"],
+                                                         cert["queries"]))
         f.write("oracle_seconds %.1f\nchunk_rows %d\n" % (secs, CHUNK))
         f.write("tree %s\n" % tree)
         for i, c in enumerate(chunks):

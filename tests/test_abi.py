@@ -32,7 +32,9 @@ def test_library_exports_every_declared_function():
 def test_struct_sizes():
     assert ctypes.sizeof(parchain.pc_merge) == 32
     assert ctypes.sizeof(parchain.pc_options) == 24
-    assert ctypes.sizeof(parchain.pc_stats) == 8 + 5 * 8 + 4 * 8 + 4 * 8 + 4 * 8 + 4 * 8 + 4 * 8
+    assert ctypes.sizeof(parchain.pc_stats) == 8 + 5 * 8 + 4 * 8 + 4 * 8 + 4 * 8 + 4 * 8 + 4 * 8 + 2 * 8 + 3 * 8
+    assert ctypes.sizeof(parchain.pc_server_options) == 32
+    assert ctypes.sizeof(parchain.pc_server_stats) == 4 + 4 + 5 * 8 + 4 * 4 + 3 * 8 + 8
 
 
 def test_version_string():
@@ -67,7 +69,20 @@ def test_hac_argument_checks_before_device_work():
     rc = lib.pc_hac(None, ctypes.cast(buf, ctypes.c_void_p), 4, 2, 0, 2, None,
                     ctypes.cast(out, ctypes.c_void_p), 0, None, None)
     assert rc == -1 and b"context" in lib.pc_last_error()
-    assert lib.pc_context_create(0, None) == -1
+    assert lib.pc_context_create(0, 0, None) == -1
+
+
+def test_precision_modes():
+    """The screening tiles' element type (pc_precision): FP32 copies take twice
+    the bytes of FP16/BF16 ones; unknown modes are rejected."""
+    f16 = pc.workspace_bytes(50_000, 64, "complete", "fp16")
+    b16 = pc.workspace_bytes(50_000, 64, "complete", "bf16")
+    f32 = pc.workspace_bytes(50_000, 64, "complete", "fp32")
+    assert f16 == b16 and f32 > f16
+    # no tiles at d = 2: the modes coincide
+    assert pc.workspace_bytes(50_000, 2, "ward", "fp32") == pc.workspace_bytes(50_000, 2, "ward", "fp16")
+    assert pc.workspace_bytes(1000, 64, "complete", 3) == 0
+    assert pc.workspace_bytes(1000, 64, "complete", -1) == 0
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -21,23 +21,26 @@ def test_gram_depth_covers_d_plus_two():
 
 
 def test_visit_prices():
-    # 16 B record + FP64 centroid; avg-2 adds its FP64 spread term,
-    # complete / average the FP32 box
-    assert bench.visit_bytes("ward", 2) == 32
-    assert bench.visit_bytes("avgsq", 2) == 40
-    assert bench.visit_bytes("complete", 2) == 48
-    assert bench.visit_bytes("average", 5) == 16 + 40 + 40
+    # FP64 centroid + size + cluster ID; avg-2 adds its FP64 spread term,
+    # complete / average the FP32 box (8d + 4 + 4 + 8d = 40 B at d = 2)
+    assert bench.visit_bytes("ward", 2) == 24
+    assert bench.visit_bytes("avgsq", 2) == 32
+    assert bench.visit_bytes("complete", 2) == 40
+    assert bench.visit_bytes("average", 5) == 40 + 8 + 40
 
 
 def test_roofline_arithmetic():
     st = {"kernels": {"ring_search": {"visits": 1_000_000}}, "point_pair_evals": 0}
-    # 2 launches taking 1 ms in total: 1e6 visits x 48 B / 2 launches = 24 MB
-    # per launch in 0.5 ms = 48 GB/s
+    # 2 launches taking 1 ms in total: 1e6 visits x 40 B / 2 launches = 20 MB
+    # per launch in 0.5 ms = 40 GB/s
     r = bench.roofline("ring_search", "complete", 2, 1.0, 2, [st])
     assert r["bound"] == "hbm" and r["unit"] == "GB/s"
-    assert r["achieved"] == pytest.approx(48.0)
-    assert r["frac"] == pytest.approx(48.0 / bench.PEAK_HBM_GBS)
-    assert r["work_per_launch"] == pytest.approx(24e6)
+    assert r["achieved"] == pytest.approx(40.0)
+    assert r["frac"] == pytest.approx(40.0 / bench.PEAK_HBM_GBS)
+    assert r["work_per_launch"] == pytest.approx(20e6)
+    if r["traffic"] is not None:
+        # measured bytes per launch over the same launch time
+        assert r["measured_frac"] == pytest.approx(r["traffic"] / 0.5e-3 / 1e9 / bench.PEAK_HBM_GBS)
     # a Gram-search kernel at d = 10 is priced as FP16 MFMA work: 2K flops per pair
     r = bench.roofline("ring_search", "ward", 10, 1.0, 1, [st])
     assert r["bound"] == "mfma" and r["achieved"] == pytest.approx(1e6 * 2 * 16 / 1e-3 / 1e12)

@@ -40,9 +40,11 @@ def run(pc, x, link, **kw):
     return Z, st
 
 
-def check_parity(pc, x, link, **kw):
+def check_parity(pc, x, link, tie_free=True, **kw):
     n = x.shape[0]
     Zo, cert = oracle.nnchain(x, link, threads=8)
+    if tie_free:
+        assert cert["min_gap"] >= 1e-10, "input not certified tie-free"
     Zg, st = run(pc, x, link, **kw)
     _trees.assert_valid(Zg, n)
     assert _trees.same_tree(Zg, Zo, n, rtol=RTOL[link]), (link, n, _trees.max_rel_height_err(Zg, Zo, n))
@@ -58,7 +60,9 @@ def test_fig1_worked_example(pc):
     # six points shaped after the paper's worked example (Sec. 1, Fig. 1):
     # four rounds, (a,b) and (c,d) in round 1, e's tie resolved towards {a,b}
     x = np.array([[0.0, 3.0], [0.6, 2.2], [3.2, 0.2], [2.0, 0.0], [0.0, 0.0], [0.0, -3.0]], np.float32)
-    Zg, st, _ = check_parity(pc, x, "complete")
+    # its round-2 tie is exact (the certificate is 0): the cluster-ID rule
+    # decides it, in the oracle and on the GPU alike
+    Zg, st, _ = check_parity(pc, x, "complete", tie_free=False)
     assert st["rounds"] == 4
     Zo, _ = oracle.nnchain(x, "complete")
     assert np.array_equal(Zg, oracle.canonical(Zo, 6))
@@ -144,10 +148,16 @@ def test_special_cases(pc):
         x[7] = x[3]
         Z = pc.hac(x, link)
         assert Z[0, 2] == 0.0 and {int(Z[0, 0]), int(Z[0, 1])} == {3, 7}
+        _trees.assert_valid_hac(x, Z, link, rtol=1e-9)
         # all points identical: every height is 0
-        Z = pc.hac(np.ones((20, 2), np.float32), link)
+        x = np.ones((20, 2), np.float32)
+        Z = pc.hac(x, link)
         assert np.all(Z[:, 2] == 0.0)
-        _trees.assert_valid(Z, 20)
+        _trees.assert_valid_hac(x, Z, link)
+        # exact ties between different distances: points on an integer grid
+        g = np.stack(np.meshgrid(np.arange(6), np.arange(5)), -1).reshape(-1, 2).astype(np.float32)
+        Z = pc.hac(g, link)
+        _trees.assert_valid_hac(g, Z, link, rtol=1e-9)
 
 
 def test_nonfinite_rejected(pc):
@@ -333,8 +343,8 @@ def test_box_tree_equals_other_searches(pc, link, d, kind, monkeypatch):
     assert np.array_equal(Zt, pc.hac(x, link))
     assert np.array_equal(Zt, pc.hac(x, link, prune=False))
     Zr, cert = oracle.nnchain(x, link, threads=8)
-    if cert["min_gap"] >= 1e-10:
-        assert _trees.same_tree(Zt, Zr, n, rtol=RTOL[link])
+    assert cert["min_gap"] >= 1e-10, "fixed input no longer certified tie-free"
+    assert _trees.same_tree(Zt, Zr, n, rtol=RTOL[link])
 
 
 @pytest.mark.parametrize("link", ["ward", "avgsq"])
@@ -351,10 +361,14 @@ def test_box_tree_edge_cases(pc, link, d, monkeypatch):
         _trees.assert_valid(Z, n)
         if cert["min_gap"] >= 1e-10:
             assert _trees.same_tree(Z, Zo, n, rtol=RTOL[link]), (n, d)
+        else:
+            # ties: any dendrogram of reciprocal-nearest merges is correct
+            _trees.assert_valid_hac(x, Z, link, rtol=1e-9)
     x = synth.uniform(300, d, 99)
     x[150:] = x[:150]  # every point twice
     Z = pc.hac(x, link)
     _trees.assert_valid(Z, 300)
+    _trees.assert_valid_hac(x, Z, link, rtol=1e-9)
     assert np.all(Z[:150, 2] == 0.0)
     assert {frozenset((int(a), int(b))) for a, b in Z[:150, :2]} == {frozenset((i, i + 150)) for i in range(150)}
     Z = pc.hac(np.ones((40, d), np.float32), link)
@@ -373,7 +387,49 @@ def test_complete_giant_pairs_block_pruning(pc, d):
     Zo, cert = oracle.nnchain(x, "complete", threads=8)
     Z, st = pc.hac(x, "complete", return_stats=True)
     assert st["kernels"]["block_search"]["visits"] > 0  # point pairs screened
-    if cert["min_gap"] >= 1e-10:
-        assert _trees.same_tree(Z, Zo, x.shape[0], rtol=0.0)
+    assert cert["min_gap"] >= 1e-10, "fixed input no longer certified tie-free"
+    assert _trees.same_tree(Z, Zo, x.shape[0], rtol=0.0)
     C = oracle.canonical(Zo, x.shape[0])
     assert Z[-1, 2] == C[-1, 2]  # the farthest pair of the final merge, bit for bit
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("n,d,kind,seed", [(3000, 10, "b", 7), (2000, 64, "b", 11), (2500, 128, "s", 12)])
+def test_precision_forms(pc, precision, link, n, d, kind, seed):
+    """The screening tiles in BF16 or FP32 operands instead of FP16 (pc_precision):
+    candidates they cannot rule out are refined in FP64 in every form, so the
+    tree matches the oracle's and the rows equal the FP16 form's; only the
+    number of refined candidates may differ."""
+    if kind == "b":
+        x = synth.blobs(n, d, 8, 0.03, seed)
+    else:
+        x = synth.sphere_blobs(n, d, 25, 0.1, seed)
+    _, cert = oracle.nnchain(x, link, threads=8)
+    assert cert["min_gap"] >= 1e-10, "fixed input no longer certified tie-free"
+    Zg, st, _ = check_parity(pc, x, link, precision=precision)
+    Z16, s16 = pc.hac(x, link, return_stats=True)
+    assert same_rows(Zg, Z16, link)
+    assert st["refined"] > 0 and s16["refined"] > 0
+    assert 0 <= st["fp64_fallbacks"] <= st["refined"]
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+@pytest.mark.parametrize("link", ["complete", "average"])
+def test_precision_forms_interval_tiles(pc, precision, link):
+    """Large candidate pairs bracketed by point-pair tiles of each element type
+    (d = 64), then refined exactly: the same rows as the FP16 form."""
+    x = synth.sphere_blobs(2000, 64, 12, 0.1, 124)
+    Z16 = pc.hac(x, link)
+    Zp, st = pc.hac(x, link, precision=precision, return_stats=True)
+    assert st["kernels"]["block_search"]["visits"] > 0  # point pairs screened
+    assert same_rows(Zp, Z16, link)
+
+
+def test_round_phase_times(pc):
+    """With timing on, the rounds' device time is split into the search, the
+    merges and the state update."""
+    x = synth.blobs(20_000, 2, 50, 0.01, 11)
+    _, st = pc.hac(x, "complete", return_stats=True, timing=True)
+    assert st["ms_nn"] > 0 and st["ms_merge"] > 0 and st["ms_update"] > 0
+    assert st["ms_nn"] + st["ms_merge"] + st["ms_update"] <= st["ms_rounds"] * 1.05

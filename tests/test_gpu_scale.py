@@ -266,3 +266,47 @@ def test_c3_d10_1m_average(pc):
     _, sizes = oracle.tree_sums(x, Z)
     structure(Z, n, sizes)
     nn_check(x, Z, "average", full_size_rows(Z, 8, k=6), max_side=100)
+
+
+# ---- whole-tree parity at full size against stored oracle digests --------
+# The digests were written by tests/golden/digests.py from the FP64 oracle's
+# accelerated mode (rows bit for bit those of the plain sequential chain).
+from tests.golden import digests as _dig  # noqa: E402
+
+DIGEST_TOL = {"ward": 0.0, "complete": 0.0, "avgsq": 1e-10}
+
+
+def _digest_case(pc, name):
+    ref = _dig.read(name)
+    link = ref["linkage"]
+    x = _dig.points(name)
+    n = x.shape[0]
+    assert n == ref["n"]
+    # the oracle certified the input tie-free at this scale (cap 2^-23 in its
+    # accelerated mode; 1e-12 is the tie threshold)
+    assert ref["min_gap"] > 1e-12 and ref["zero_best"] == 0
+    Z = pc.hac(x, link)
+    tree, chunks, keys = _dig.summarise(Z, n)
+    print("%s: GPU tree digest %s, oracle %s" % (name, tree[:16], ref["tree"][:16]), flush=True)
+    assert tree == ref["tree"], "different tree"
+    if DIGEST_TOL[link] == 0.0:
+        bad = [i for i, (a, b) in enumerate(zip(chunks, ref["chunks"])) if a != b]
+        assert len(chunks) == len(ref["chunks"]) and not bad, "rows differ in chunks %s" % bad[:10]
+    # sampled heights, by merge identity
+    at = {tuple(k): i for i, k in enumerate(keys.tolist())}
+    for k, h in ref["heights"].items():
+        g = Z[at[k], 2]
+        assert abs(g - h) <= DIGEST_TOL[link] * abs(h), (k, g, h)
+
+
+@pytest.mark.parametrize("name", ["blob50_1m_d2_ward", "blob50_1m_d2_complete", "blob50_1m_d2_avgsq"])
+def test_whole_tree_digest_1m(pc, name):
+    """The headline 1M-point input: the whole dendrogram against the oracle's
+    (Ward and complete: every row bit for bit; avg-2: the same tree and
+    sampled heights within 1e-10)."""
+    _digest_case(pc, name)
+
+
+def test_whole_tree_digest_10m_ward(pc):
+    """10,000,000 points of the same law under Ward linkage: every row."""
+    _digest_case(pc, "blob50_10m_d2_ward")

@@ -33,7 +33,8 @@ def test_budget_and_slots_respected():
     assert st["completed"] == len(sizes) and st["failed"] == 0 and st["queued"] == 0
     assert st["peak_bytes_in_use"] <= budget
     assert 2 <= st["peak_running"] <= 3
-    assert st["bytes_in_use"] == 0
+    # idle slots count only what their contexts keep, within their share
+    assert st["bytes_in_use"] <= budget
 
 
 def test_requests_overlap():
@@ -88,6 +89,35 @@ def test_first_fit_then_no_overtaking():
     assert sum(s < ib["t_start_ms"] for s in starts) >= 2
     # ... at most 16 of them
     assert sum(s < ib["t_start_ms"] for s in starts) <= 16
+
+
+def test_growth_beyond_the_footprint_stays_within_budget():
+    """Requests whose device need grows to 2.5x their initial footprint (as
+    candidate records do): each stops at its reservation, goes back to the
+    queue with twice the reservation and finishes; the bytes in use never
+    exceed the budget, and none fails."""
+    sizes = [800, 2000, 1200, 3000, 600, 1500, 2500, 1000]
+    budget = int(2.6 * fp(3000)) + fp(2000)
+    with pc.Server(slots=4, hbm_budget_bytes=budget, fake_us_per_kpoint=US_PER_KPT,
+                   fake_growth=2.5) as srv:
+        ts = [srv.submit(pts(n, i), "ward") for i, n in enumerate(sizes)]
+        infos = [srv.result(t)[1] for t in ts]
+        st = srv.stats()
+    assert st["completed"] == len(sizes) and st["failed"] == 0
+    assert st["requeued"] >= len(sizes)  # each needed one larger reservation
+    assert st["peak_bytes_in_use"] <= budget
+    for n, info in zip(sizes, infos):
+        assert info["status"] == 0 and info["footprint_bytes"] >= 2.5 * fp(n)
+
+
+def test_growth_beyond_the_budget_fails():
+    with pc.Server(slots=2, hbm_budget_bytes=int(1.5 * fp(2000)), fake_us_per_kpoint=US_PER_KPT,
+                   fake_growth=3.0) as srv:
+        t = srv.submit(pts(2000), "ward")
+        with pytest.raises(PCError) as e:
+            srv.result(t)
+        assert e.value.status == -3
+        assert srv.stats()["failed"] == 1
 
 
 def test_cancel_and_shutdown():
