@@ -174,6 +174,32 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
                  void *stream, pc_stats *stats);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): pc_hac on
+ * device pointers that allocates nothing. Every buffer of the call is a
+ * window of one static device array of PC_NOALLOC_SCRATCH_BYTES per GPU (held
+ * by each GPU the library runs on until the process ends; its device address
+ * is taken once per device by pc_context_create). No hipMalloc, hipFree or
+ * other allocating routine is called.
+ *   points, out      device pointers (n x d float32 row-major; n-1 rows)
+ *   ctx, linkage, opt, stream, stats   as for pc_hac
+ * Records cannot grow here: the Gram search runs its chain tails in smaller
+ * batches instead, the ring search re-walks its rings, and a round that needs
+ * more pair-list, tile or filter space than the scratch holds fails with
+ * PC_ERR_OUT_OF_MEMORY, as does an input whose workspace does not fit (the
+ * limit depends on n, d and the linkage: Ward and avg-2 at d = 2 reach about
+ * 600K points, complete and average fewer). The cluster-pair cache is
+ * smaller or off; the rows are pc_hac's (average linkage: heights within
+ * 1e-12 relative, as with any cache size). The scratch keeps the last call's
+ * contents, and the call clears what must start empty. Calls on one GPU share
+ * its array: calls that overlap in time on one GPU (any context, any stream)
+ * race and give wrong results.
+ */
+#define PC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+pc_status pc_hac_noalloc(pc_context *ctx, const float *points, int64_t n, int32_t d, int32_t linkage,
+                         const pc_options *opt, pc_merge *out, void *stream, pc_stats *stats);
+
+/*
  * ---- Serving: many requests on one device --------------------------------
  * A server keeps up to `slots` requests on the GPU at once, each on its own
  * context and HIP stream, so the rounds of different requests overlap on the

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -161,13 +162,49 @@ struct Buf {
   size_t bytes = 0;
 };
 
+// The allocation-free entry point (pc_hac_noalloc) carves every buffer of its
+// call out of this array; each device that loads the library holds its own
+// copy until the process ends. Host code must not pass the array's name to a
+// kernel: on the host it is only a stand-in. Its device address is taken once
+// per device with hipGetSymbolAddress (scratch_address) and used instead.
+static __device__ __align__(256) unsigned char scratch[PC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's scratch array; call with `dev` current
+hipError_t scratch_address(int dev, void **out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// The device buffers of a call: the context's own (grown on demand, kept
+// between calls) or windows of the static scratch array (fixed: never grown).
+struct Bufs {
+  Buf ws, pairs, tiles, part, fidx, cand, cache[2];
+  bool fixed = false;
+};
+
 }  // namespace
 
 struct pc_context {
   int device = 0;
   size_t budget = 0;         // most device bytes the context may hold (0: no limit)
   bool over_budget = false;  // the last call stopped at the budget
-  Buf ws, pairs, tiles, part, fidx, cand, cache[2];
+  Bufs own;
+  Bufs *cur = &own;          // the buffers of the running call
+  void *scratch = nullptr;   // this device's static scratch array (device address)
+  hipError_t scratch_error = hipSuccess;
   Counters *hcnt = nullptr;  // pinned host mirror of the device counters
   hipEvent_t ev[4] = {};
   hipEvent_t tev[8] = {};
@@ -178,13 +215,17 @@ struct pc_context {
 namespace {
 
 size_t held_bytes(const pc_context *c) {
-  size_t b = c->ws.bytes + c->pairs.bytes + c->tiles.bytes + c->part.bytes + c->fidx.bytes + c->cand.bytes;
-  return b + c->cache[0].bytes + c->cache[1].bytes;
+  const Bufs &o = c->own;
+  size_t b = o.ws.bytes + o.pairs.bytes + o.tiles.bytes + o.part.bytes + o.fidx.bytes + o.cand.bytes;
+  return b + o.cache[0].bytes + o.cache[1].bytes;
 }
 
-// would growing b to `bytes` keep the context within its budget?
+// can b hold `bytes`, growing within the context's budget if need be?
+// (fixed buffers never grow)
 bool fits(const pc_context *c, const Buf &b, size_t bytes) {
-  if (b.bytes >= bytes || !c->budget) return true;
+  if (b.bytes >= bytes) return true;
+  if (c->cur->fixed) return false;
+  if (!c->budget) return true;
   return held_bytes(c) - b.bytes + bytes <= c->budget;
 }
 
@@ -228,6 +269,16 @@ pc_status pc_context_create(int device, size_t hbm_budget_bytes, pc_context **ou
   for (int i = 0; e == hipSuccess && i < 4; ++i) e = hipEventCreate(&c->ev[i]);
   for (int i = 0; e == hipSuccess && i < 8; ++i) e = hipEventCreate(&c->tev[i]);
   for (int i = 0; e == hipSuccess && i < 4; ++i) e = hipEventCreate(&c->rev[i]);
+  if (e == hipSuccess) {
+    // the allocation-free entry point's array on this device; a failure here
+    // is reported by that entry point (c->scratch stays null), not by pc_hac
+    const hipError_t se = scratch_address(dev, &c->scratch);
+    if (se != hipSuccess) {
+      c->scratch = nullptr;
+      c->scratch_error = se;
+      (void)hipGetLastError();
+    }
+  }
   if (e != hipSuccess) {
     pc_context_destroy(c);
     return fail(PC_ERR_DEVICE, std::string("context setup: ") + hipGetErrorString(e));
@@ -252,7 +303,8 @@ bool context_over_budget(const pc_context *c) { return c->over_budget; }
 
 void context_trim(pc_context *c) {
   hipSetDevice(c->device);
-  for (Buf *b : {&c->ws, &c->pairs, &c->tiles, &c->part, &c->fidx, &c->cand, &c->cache[0], &c->cache[1]}) {
+  Bufs &o = c->own;
+  for (Buf *b : {&o.ws, &o.pairs, &o.tiles, &o.part, &o.fidx, &o.cand, &o.cache[0], &o.cache[1]}) {
     if (b->p) hipFree(b->p);
     b->p = nullptr;
     b->bytes = 0;
@@ -266,14 +318,9 @@ void pc_context_destroy(pc_context *c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipDeviceSynchronize();
-  if (c->ws.p) hipFree(c->ws.p);
-  if (c->pairs.p) hipFree(c->pairs.p);
-  if (c->tiles.p) hipFree(c->tiles.p);
-  if (c->part.p) hipFree(c->part.p);
-  if (c->fidx.p) hipFree(c->fidx.p);
-  if (c->cand.p) hipFree(c->cand.p);
-  for (int i = 0; i < 2; ++i)
-    if (c->cache[i].p) hipFree(c->cache[i].p);
+  Bufs &o = c->own;
+  for (Buf *b : {&o.ws, &o.pairs, &o.tiles, &o.part, &o.fidx, &o.cand, &o.cache[0], &o.cache[1]})
+    if (b->p) hipFree(b->p);
   if (c->hcnt) hipHostFree(c->hcnt);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) hipEventDestroy(c->ev[i]);
@@ -318,9 +365,9 @@ constexpr long long kMaxRecord = 1LL << 30;
 // Scan partials: one per 1024 elements of the longest scan of the call.
 static pc_status grow_part(pc_context *ctx, State &S, long long longest_scan) {
   const long long need = longest_scan / 1024 + 1024;
-  HIPCHK(grow(ctx, ctx->part, (size_t)need * sizeof(long long)));
-  S.part = (long long *)ctx->part.p;
-  S.part_cap = (long long)(ctx->part.bytes / sizeof(long long));
+  HIPCHK(grow(ctx, ctx->cur->part, (size_t)need * sizeof(long long)));
+  S.part = (long long *)ctx->cur->part.p;
+  S.part_cap = (long long)(ctx->cur->part.bytes / sizeof(long long));
   return PC_OK;
 }
 
@@ -334,9 +381,9 @@ constexpr size_t kCandBytes = 3 * sizeof(double) + sizeof(long long) + sizeof(in
 static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
   if (cap > kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round needs more than 2^30 cluster pairs");
   const size_t per = kPairBytes;
-  HIPCHK(grow(ctx, ctx->pairs, (size_t)cap * per + 1024));
-  char *b = (char *)ctx->pairs.p;
-  const long long pc = (long long)((ctx->pairs.bytes - 1024) / per);
+  HIPCHK(grow(ctx, ctx->cur->pairs, (size_t)cap * per + 1024));
+  char *b = (char *)ctx->cur->pairs.p;
+  const long long pc = (long long)((ctx->cur->pairs.bytes - 1024) / per);
   S.pair_cap = pc;
   S.pr_tile0 = (long long *)b;
   S.pr_cbase = S.pr_tile0 + pc;
@@ -353,26 +400,26 @@ static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
 
 static pc_status grow_fidx(pc_context *ctx, State &S, long long cap) {
   if (cap > 8 * kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round's pair filter needs too many points");
-  HIPCHK(grow(ctx, ctx->fidx, (size_t)cap * sizeof(int)));
-  S.fidx = (int *)ctx->fidx.p;
-  S.fidx_cap = (long long)(ctx->fidx.bytes / sizeof(int));
+  HIPCHK(grow(ctx, ctx->cur->fidx, (size_t)cap * sizeof(int)));
+  S.fidx = (int *)ctx->cur->fidx.p;
+  S.fidx_cap = (long long)(ctx->cur->fidx.bytes / sizeof(int));
   return PC_OK;
 }
 
 static pc_status grow_tiles(pc_context *ctx, State &S, long long cap) {
-  HIPCHK(grow(ctx, ctx->tiles, (size_t)cap * sizeof(double)));
-  S.tile_v = (double *)ctx->tiles.p;
-  S.tile_cap = (long long)(ctx->tiles.bytes / sizeof(double));
+  HIPCHK(grow(ctx, ctx->cur->tiles, (size_t)cap * sizeof(double)));
+  S.tile_v = (double *)ctx->cur->tiles.p;
+  S.tile_cap = (long long)(ctx->cur->tiles.bytes / sizeof(double));
   return PC_OK;
 }
 
 static pc_status grow_cand(pc_context *ctx, State &S, long long cap) {
   if (cap > kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round needs more than 2^30 recorded candidates");
   const size_t per = kCandBytes;
-  HIPCHK(grow(ctx, ctx->cand, (size_t)cap * per + 1024));
-  const long long cc = (long long)((ctx->cand.bytes - 1024) / per);
+  HIPCHK(grow(ctx, ctx->cur->cand, (size_t)cap * per + 1024));
+  const long long cc = (long long)((ctx->cur->cand.bytes - 1024) / per);
   S.cand_cap = cc;
-  S.cd_lb = (double *)ctx->cand.p;
+  S.cd_lb = (double *)ctx->cur->cand.p;
   S.cd_v = S.cd_lb + cc;
   S.cd_l0 = S.cd_v + cc;
   S.cd_tile0 = (long long *)(S.cd_l0 + cc);  // 32 cc bytes in: the int4 records stay 16-byte aligned
@@ -384,9 +431,77 @@ static pc_status grow_cand(pc_context *ctx, State &S, long long cap) {
   return grow_part(ctx, S, std::max<long long>(cc, 2LL * S.n + 64));
 }
 
-pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int points_on_device,
-                 int32_t linkage, const pc_options *opt, pc_merge *out, int out_on_device, void *stream,
-                 pc_stats *stats) {
+// Windows of the scratch array for one allocation-free call: the layout
+// (`ws` bytes), the scan partials, then the candidate record, pair list, tile
+// partials or filter indices and the two cache tables in fixed shares of what
+// is left. cache_cap: entries per cache table (a power of two, 0: no cache).
+static pc_status carve_scratch(char *base, size_t ws, int64_t n, int d, int linkage, int cache_slots, Bufs &B,
+                               unsigned long long &cache_cap) {
+  const size_t total = PC_NOALLOC_SCRATCH_BYTES;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t off = 0;
+  auto take = [&](Buf &b, size_t bytes) {
+    b.p = base + off;
+    b.bytes = bytes;
+    off = al(off + bytes);
+  };
+  cache_cap = 0;
+  if (al(ws) + (1u << 20) > total)
+    return fail(PC_ERR_OUT_OF_MEMORY, "input too large for the allocation-free scratch buffer");
+  take(B.ws, ws);
+  // scan partials for the longest scan a record of this scratch can need
+  const size_t left = total - off;
+  const long long longest = std::max<long long>(2 * n + 64, (long long)(left / kPairBytes) + 1);
+  take(B.part, (size_t)(longest / 1024 + 1024) * sizeof(long long));
+  if (off + (1u << 20) > total)
+    return fail(PC_ERR_OUT_OF_MEMORY, "input too large for the allocation-free scratch buffer");
+  const size_t rest = total - off - 8 * 256;  // alignment slack of the windows below
+  const bool gram = d >= kGramMinDim && d <= kGramMaxDim;
+  double fc = 0.0, fp = 0.0, ft = 0.0, ff = 0.0, fk = 0.0;  // shares of the rest
+  if (centroid_link(linkage)) {
+    fc = gram ? 1.0 : 0.0;
+  } else if (linkage == kComplete) {
+    fk = cache_slots > 0 ? 0.15 : 0.0;
+    fc = 0.3;
+    fp = 0.2;
+    ff = 0.5 - fk;
+  } else {
+    fk = cache_slots > 0 ? 0.15 : 0.0;
+    fc = 0.3;
+    fp = 0.25;
+    ft = 0.45 - fk;
+  }
+  auto share = [&](double f) { return std::max<size_t>((size_t)(f * (double)rest) & ~(size_t)255, 256); };
+  take(B.cand, share(fc));
+  take(B.pairs, share(fp));
+  take(B.tiles, share(ft));
+  take(B.fidx, share(ff));
+  if (fk > 0.0) {
+    unsigned long long cap = 1;
+    while (2 * (cap * 2) * 2 * sizeof(unsigned long long) <= share(fk)) cap *= 2;
+    if (cap >= 1024) {
+      cache_cap = cap;
+      take(B.cache[0], cap * 2 * sizeof(unsigned long long));
+      take(B.cache[1], cap * 2 * sizeof(unsigned long long));
+    }
+  }
+  if (off > total) return fail(PC_ERR_OUT_OF_MEMORY, "allocation-free scratch buffer overrun");
+  if ((!centroid_link(linkage) || gram) && B.cand.bytes < 4096 * kCandBytes + 1024)
+    return fail(PC_ERR_OUT_OF_MEMORY, "input too large for the allocation-free scratch buffer");
+  B.fixed = true;
+  return PC_OK;
+}
+
+// the initial size of a record: `want` entries, or what a fixed window holds
+static long long initial_cap(const pc_context *ctx, const Buf &b, long long want, size_t per, size_t extra) {
+  if (!ctx->cur->fixed) return want;
+  const long long c = (long long)((b.bytes > extra ? b.bytes - extra : 0) / per);
+  return std::max<long long>(1, std::min(want, c));
+}
+
+static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32_t d, int points_on_device,
+                          int32_t linkage, const pc_options *opt, pc_merge *out, int out_on_device, void *stream,
+                          pc_stats *stats, bool noalloc) {
   if (!ctx) return fail(PC_ERR_INVALID_ARG, "context is NULL");
   if (!points) return fail(PC_ERR_INVALID_ARG, "points is NULL");
   if (n < 1) return fail(PC_ERR_INVALID_ARG, "n must be >= 1");
@@ -429,10 +544,26 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   State S;
   memset(&S, 0, sizeof(S));
   const size_t need = layout(S, nullptr, n, d, linkage, !points_on_device, elem);
-  HIPCHK(grow(ctx, ctx->ws, need));
+  // allocation-free call: every buffer is a window of the scratch array
+  Bufs fixed;
+  struct Restore {
+    pc_context *c;
+    ~Restore() { c->cur = &c->own; }
+  } restore{ctx};
+  unsigned long long fixed_cache = 0;
+  if (noalloc) {
+    if (!ctx->scratch)
+      return fail(PC_ERR_DEVICE, std::string("no scratch address for this device: ") +
+                                     hipGetErrorString(ctx->scratch_error));
+    pc_status st = carve_scratch((char *)ctx->scratch, need, n, d, linkage, cache_slots, fixed, fixed_cache);
+    if (st != PC_OK) return st;
+    if (!fixed_cache) cache_slots = 0;  // no room for the cache: values are recomputed (same rows)
+    ctx->cur = &fixed;
+  }
+  HIPCHK(grow(ctx, ctx->cur->ws, need));
   float *xstage = nullptr;
   pc_merge *rstage = nullptr;
-  layout(S, (char *)ctx->ws.p, n, d, linkage, !points_on_device, elem, &xstage, &rstage);
+  layout(S, (char *)ctx->cur->ws.p, n, d, linkage, !points_on_device, elem, &xstage, &rstage);
   S.n = (int)n;
   S.d = d;
   S.linkage = linkage;
@@ -485,18 +616,22 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
     if (st != PC_OK) return st;
   }
   if (centroid_link(linkage) && gram_ok) {
-    pc_status st = grow_cand(ctx, S, std::max<long long>(1 << 22, 4 * n));
+    pc_status st = grow_cand(ctx, S, initial_cap(ctx, ctx->cur->cand, std::max<long long>(1 << 22, 4 * n),
+                                                 kCandBytes, 1024));
     if (st != PC_OK) return st;
     if (const char *e = getenv("PC_TEST_CAND_CAP")) S.cand_cap = std::min<long long>(S.cand_cap, atoll(e));
   }
   if (!centroid_link(linkage)) {
-    pc_status st = grow_pairs(ctx, S, std::max<long long>(1 << 20, 2 * n));
+    pc_status st = grow_pairs(ctx, S, initial_cap(ctx, ctx->cur->pairs, std::max<long long>(1 << 20, 2 * n),
+                                                  kPairBytes, 1024));
     if (st != PC_OK) return st;
-    st = grow_tiles(ctx, S, linkage == kAverage ? (1 << 22) : 1);
+    st = grow_tiles(ctx, S, initial_cap(ctx, ctx->cur->tiles, linkage == kAverage ? (1 << 22) : 1,
+                                        sizeof(double), 0));
     if (st != PC_OK) return st;
-    st = grow_fidx(ctx, S, linkage == kComplete ? std::max<long long>(1 << 22, 4 * n) : 1);
+    st = grow_fidx(ctx, S, initial_cap(ctx, ctx->cur->fidx, linkage == kComplete ? std::max<long long>(1 << 22, 4 * n) : 1,
+                                       sizeof(int), 0));
     if (st != PC_OK) return st;
-    st = grow_cand(ctx, S, std::max<long long>(1 << 22, 4 * n));
+    st = grow_cand(ctx, S, initial_cap(ctx, ctx->cur->cand, std::max<long long>(1 << 22, 4 * n), kCandBytes, 1024));
     if (st != PC_OK) return st;
     // test hooks: shrink the candidate record / pair list to exercise their
     // overflow paths (capacities only ever limit, never extend, the buffers)
@@ -510,15 +645,16 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   if (cache_slots > 0) {
     unsigned long long cap = 1ull << 16;
     while (cap < (unsigned long long)n * (unsigned long long)cache_slots && cap < (1ull << 31)) cap <<= 1;
+    if (ctx->cur->fixed) cap = std::min(cap, fixed_cache);
     // test hook: a small table exercises rebuilds and full probe windows
     if (const char *e = getenv("PC_TEST_CACHE_CAP")) {
       unsigned long long want = (unsigned long long)atoll(e), c2 = 64;
       while (c2 < want) c2 <<= 1;
       if (c2 < cap) cap = c2;
     }
-    for (int i = 0; i < 2; ++i) HIPCHK(grow(ctx, ctx->cache[i], (size_t)cap * 2 * sizeof(unsigned long long)));
+    for (int i = 0; i < 2; ++i) HIPCHK(grow(ctx, ctx->cur->cache[i], (size_t)cap * 2 * sizeof(unsigned long long)));
     S.cache_mask = cap - 1;
-    S.ck = (unsigned long long *)ctx->cache[0].p;
+    S.ck = (unsigned long long *)ctx->cur->cache[0].p;
     S.cv = S.ck + cap;
     launch_cache_clear(S, S.ck, S.cv, S.cache_mask, s);
     HIPCHK(hipGetLastError());
@@ -636,7 +772,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
           // (beyond the record limit or the context's budget: fewer terminals)
           if (h.cand_overflow) {
             const long long want = h.n_cand + h.n_cand / 2 + 1024;
-            if (want <= kMaxRecord && fits(ctx, ctx->cand, (size_t)want * kCandBytes + 1024)) {
+            if (want <= kMaxRecord && fits(ctx, ctx->cur->cand, (size_t)want * kCandBytes + 1024)) {
               pc_status st = grow_cand(ctx, S, want);
               if (st != PC_OK) return st;
             } else {
@@ -645,7 +781,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
           }
           if (pover) {
             const long long want = std::max<long long>(h.n_pairs, h.n_pend) * 3 / 2 + 1024;
-            if (want <= kMaxRecord && fits(ctx, ctx->pairs, (size_t)want * kPairBytes + 1024)) {
+            if (want <= kMaxRecord && fits(ctx, ctx->cur->pairs, (size_t)want * kPairBytes + 1024)) {
               pc_status st = grow_pairs(ctx, S, want);
               if (st != PC_OK) return st;
             } else {
@@ -688,9 +824,13 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        // later rounds: a larger record, if the budget (or a fixed scratch
+        // window) allows; otherwise they re-walk too
         const long long want = std::min<long long>(h.n_cand + h.n_cand / 2 + 1024, kMaxRecord);
-        pc_status st = grow_cand(ctx, S, want);
-        if (st != PC_OK) return st;
+        if (fits(ctx, ctx->cur->cand, (size_t)want * kCandBytes + 1024)) {
+          pc_status st = grow_cand(ctx, S, want);
+          if (st != PC_OK) return st;
+        }
       }
       if (h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap) {
         S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;  // the round is redone
@@ -735,7 +875,7 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
       // rebuild: keep only entries whose two clusters are still alive
       const int nxt = 1 - cache_cur;
       unsigned long long *ok = S.ck, *ov = S.cv;
-      S.ck = (unsigned long long *)ctx->cache[nxt].p;
+      S.ck = (unsigned long long *)ctx->cur->cache[nxt].p;
       S.cv = S.ck + (S.cache_mask + 1);
       launch_cache_clear(S, S.ck, S.cv, S.cache_mask, s);
       launch_cache_rebuild(S, ok, ov, S.cache_mask, s);
@@ -799,6 +939,17 @@ pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int
   }
   g_err.clear();
   return PC_OK;
+}
+
+pc_status pc_hac(pc_context *ctx, const float *points, int64_t n, int32_t d, int points_on_device,
+                 int32_t linkage, const pc_options *opt, pc_merge *out, int out_on_device, void *stream,
+                 pc_stats *stats) {
+  return hac_impl(ctx, points, n, d, points_on_device, linkage, opt, out, out_on_device, stream, stats, false);
+}
+
+pc_status pc_hac_noalloc(pc_context *ctx, const float *points, int64_t n, int32_t d, int32_t linkage,
+                         const pc_options *opt, pc_merge *out, void *stream, pc_stats *stats) {
+  return hac_impl(ctx, points, n, d, 1, linkage, opt, out, 1, stream, stats, true);
 }
 
 }  // extern "C"

@@ -112,7 +112,7 @@ class pc_server_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("struct_size", "reserved")}
 
 
-EXPORTS = ["pc_context_create", "pc_context_destroy", "pc_hac_workspace_bytes", "pc_hac",
+EXPORTS = ["pc_context_create", "pc_context_destroy", "pc_hac_workspace_bytes", "pc_hac", "pc_hac_noalloc",
            "pc_last_error", "pc_version", "pc_server_create", "pc_server_submit", "pc_server_poll",
            "pc_server_wait", "pc_server_cancel", "pc_server_release", "pc_server_get_stats",
            "pc_server_destroy"]
@@ -138,6 +138,8 @@ def load_library(path: str | None = None):
         lib.pc_hac.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
                                vp, vp, ctypes.c_int, vp, vp]
         lib.pc_hac.restype = ctypes.c_int
+        lib.pc_hac_noalloc.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
+        lib.pc_hac_noalloc.restype = ctypes.c_int
         lib.pc_last_error.argtypes = []
         lib.pc_last_error.restype = ctypes.c_char_p
         lib.pc_version.argtypes = []
@@ -223,6 +225,19 @@ class Context:
                              1 if points_on_device else 0, _link(linkage), ctypes.byref(opt),
                              ctypes.c_void_p(out), 1 if out_on_device else 0,
                              ctypes.c_void_p(stream or 0), ctypes.byref(st) if stats else None)
+        _check(self.lib, rc)
+        return st.as_dict()
+
+    def hac_noalloc(self, points, n: int, d: int, linkage, out, *, stream=None, prune: bool = True,
+                    timing: bool = False, cache_slots: int = -1, precision="fp16"):
+        """pc_hac_noalloc: ``points``/``out`` are device addresses; the call
+        allocates no device memory (the library's static scratch array)."""
+        opt = _options(prune, timing, cache_slots, precision)
+        st = pc_stats()
+        st.struct_size = ctypes.sizeof(pc_stats)
+        rc = self.lib.pc_hac_noalloc(self.handle, ctypes.c_void_p(points), int(n), int(d), _link(linkage),
+                                     ctypes.byref(opt), ctypes.c_void_p(out), ctypes.c_void_p(stream or 0),
+                                     ctypes.byref(st))
         _check(self.lib, rc)
         return st.as_dict()
 
