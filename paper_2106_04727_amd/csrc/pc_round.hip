@@ -3883,7 +3883,13 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
   k_act_pass<<<gb, kBlock, 0, s>>>(S, round);
   scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, &S.cnt->n_term, S.part, s);
   k_scatter_flagged<<<gb, kBlock, 0, s>>>(S.act, S.flags, S.scan, &S.cnt->n_act, S.term);
-  if (S.d <= kGridMaxDim && S.prune && !S.gram && !S.tree) {
+  // Few active clusters: a block per terminal scans all of them (every
+  // candidate's bounds and values are those of the ring search, so the rows
+  // are the same), which beats a thread walking grid rings in latency; the
+  // grid is then not built.
+  const bool full = S.full_scan_max > 0 && nact <= S.full_scan_max && round > 0 && S.d <= kGridMaxDim &&
+                    S.prune && !S.gram && !S.tree;
+  if (S.d <= kGridMaxDim && S.prune && !S.gram && !S.tree && !full) {
     k_grid_params<<<1, 1, 0, s>>>(S, S.cell_cap);
     k_zero_cells<<<nblk(nact + 1, 2048), kBlock, 0, s>>>(S);
     k_cell_count<<<gb, kBlock, 0, s>>>(S);
@@ -3905,6 +3911,20 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
     k_term_pos<<<gb, kBlock, 0, s>>>(S);
     if (S.linkage == kWard) launch_tree_search<kWard>(S, nact, s);
     else launch_tree_search<kAvgSq>(S, nact, s);
+    return;
+  }
+  if (full) {
+    const size_t sm = (size_t)S.d * (sizeof(double) + 2 * sizeof(float));
+    const int fb = nblk((long long)nact * kBlock, 2048);
+    tmark(S, 1, false, s);
+    switch (S.linkage) {
+    case kWard: k_nn_full<kWard><<<fb, kBlock, sm, s>>>(S, nullptr, nullptr); break;
+    case kAvgSq: k_nn_full<kAvgSq><<<fb, kBlock, sm, s>>>(S, nullptr, nullptr); break;
+    case kComplete: k_nn_full<kComplete><<<fb, kBlock, sm, s>>>(S, nullptr, nullptr); break;
+    default: k_nn_full<kAverage><<<fb, kBlock, sm, s>>>(S, nullptr, nullptr); break;
+    }
+    tmark(S, 1, true, s);
+    need_pairs = !centroid_link(S.linkage);
     return;
   }
   // Round 0 of complete linkage: every cluster is one point, where the

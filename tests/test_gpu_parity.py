@@ -433,3 +433,31 @@ def test_round_phase_times(pc):
     _, st = pc.hac(x, "complete", return_stats=True, timing=True)
     assert st["ms_nn"] > 0 and st["ms_merge"] > 0 and st["ms_update"] > 0
     assert st["ms_nn"] + st["ms_merge"] + st["ms_update"] <= st["ms_rounds"] * 1.05
+
+
+@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("law", ["uniform_fill", "gaussian_disc"])
+@pytest.mark.parametrize("d,n", [(2, 5000), (5, 3000)])
+def test_parity_paper_laws(pc, link, law, d, n):
+    """The paper's own synthetic laws (UniformFill, GaussianDisc; Sec. 6 data
+    sets), drawn here at sizes the oracle finishes in seconds: every linkage
+    on the 2-D grid and the 5-D search paths against the oracle."""
+    x = getattr(synth, law)(n, d, 500 + d)
+    check_parity(pc, x, link)
+
+
+@pytest.mark.parametrize("link,d", [("ward", 2), ("avgsq", 2), ("complete", 2), ("average", 2),
+                                    ("complete", 3), ("average", 3)])
+def test_full_scan_rounds_equal_ring_search(pc, link, d, monkeypatch):
+    """Rounds with few active clusters scan them all (a block per terminal)
+    instead of walking grid rings; the rows do not depend on where that
+    switch happens: never, the default, or from the second round on."""
+    x = synth.blobs(20_000 if link in ("ward", "avgsq") else 6_000, d, 50, 0.01, 11 + d)
+    monkeypatch.setenv("PC_FULL_SCAN_MAX", "0")
+    Z0 = pc.hac(x, link)
+    monkeypatch.delenv("PC_FULL_SCAN_MAX")
+    Z1 = pc.hac(x, link)
+    monkeypatch.setenv("PC_FULL_SCAN_MAX", "1000000000")
+    Z2, st = pc.hac(x, link, return_stats=True)
+    assert st["kernels"]["block_search"]["visits"] > 0  # the full scan ran
+    assert same_rows(Z0, Z1, link) and same_rows(Z0, Z2, link)

@@ -258,6 +258,17 @@ def test_c4_d128_200k(pc, link):
     nn_check(x, Z, link, full_size_rows(Z, 7))
 
 
+def test_c3_d10_1m_blobs_average(pc):
+    """1,000,000 points in [0,1]^10 from 100 Gaussians (sigma 0.02), average
+    linkage (the second C3 input)."""
+    x = synth.WORKLOADS["blob100_1m_d10"]()
+    Z = pc.hac(x, "average")
+    n = x.shape[0]
+    _, sizes = oracle.tree_sums(x, Z)
+    structure(Z, n, sizes)
+    nn_check(x, Z, "average", full_size_rows(Z, 18, k=6), max_side=100)
+
+
 def test_c3_d10_1m_average(pc):
     """1,000,000 uniform points in [0,1]^10, average linkage (the C3 workload)."""
     x = synth.WORKLOADS["u1m_d10"]()
@@ -282,9 +293,13 @@ def _digest_case(pc, name):
     x = _dig.points(name)
     n = x.shape[0]
     assert n == ref["n"]
-    # the oracle certified the input tie-free at this scale (cap 2^-23 in its
-    # accelerated mode; 1e-12 is the tie threshold)
-    assert ref["min_gap"] > 1e-12 and ref["zero_best"] == 0
+    # no duplicated points; the tie certificate (capped at 2^-23 in the
+    # oracle's accelerated mode) is recorded: at 1M points of float32 data an
+    # exact equal-distance pair among the ~3M queries can occur (complete
+    # linkage here), and both sides then decide it by the same (value, cluster
+    # ID) rule, so the whole tree is still compared
+    assert ref["zero_best"] == 0
+    print("%s: oracle tie certificate %.3g" % (name, ref["min_gap"]), flush=True)
     Z = pc.hac(x, link)
     tree, chunks, keys = _dig.summarise(Z, n)
     print("%s: GPU tree digest %s, oracle %s" % (name, tree[:16], ref["tree"][:16]), flush=True)
