@@ -21,7 +21,8 @@ kernel's roofline; one run each on the paper's own synthetic laws (2U1M, 2G1M,
 off and the cluster-pair cache size (0, 16, 64, 256 slots per cluster); the
 serving leg (a trace of requests of uneven n, d and linkage: one at a time,
 open loop at 0.8 x the one-at-a-time capacity with p50/p99 latency, all at
-once).
+once); the BF16 and FP32 forms of the screening tiles beside the FP16 default at
+d = 10 and d = 128.
 """
 from __future__ import annotations
 
@@ -33,6 +34,11 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+def log(msg):
+    """Progress line on stderr (stdout carries the one JSON result line)."""
+    print("[bench %s] %s" % (time.strftime("%H:%M:%S"), msg), file=sys.stderr, flush=True)
+
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_VEC_TFLOPS = 78.6
@@ -66,6 +72,15 @@ def gram_kp(d):
     return 144
 
 
+def point_kp(d):
+    """MFMA depth of the interval screening's point tiles (d alone: their norm
+    terms are added outside the MFMA)."""
+    for kp in (16, 32, 64, 80):
+        if d <= kp:
+            return kp
+    return 128
+
+
 def roofline(kname, link, d, ms, nl, sts):
     """Roofline entry of the step's dominant kernel: algorithmic work per
     launch (unit cost x units counted by the library) / average launch time
@@ -89,12 +104,13 @@ def roofline(kname, link, d, ms, nl, sts):
         r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
              "note": "box-tree search: visits x record bytes (the slot also holds Gram pass 0 rounds)"}
     elif gram and kname in ("ring_search", "ring_emit", "block_search"):
-        # Gram passes (centroid pairs) and interval tiles (point pairs): FP16 MFMA,
-        # 2 x K flops per pair
-        work = visits * 2 * gram_kp(d) / nl
+        # Gram passes (centroid pairs, K = d + 2 padded) and interval tiles
+        # (point pairs, K = d padded): FP16 MFMA, 2 x K flops per pair
+        kp = point_kp(d) if kname == "block_search" else gram_kp(d)
+        work = visits * 2 * kp / nl
         achieved = work / (avg_ms / 1000.0) / 1e12
         r = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
-             "note": "FP16 MFMA tiles; work = pairs x 2K flops (K = %d)" % gram_kp(d)}
+             "note": "FP16 MFMA tiles; work = pairs x 2K flops (K = %d)" % kp}
     else:
         work = visits * visit_bytes(link, d) / nl
         achieved = work / (avg_ms / 1000.0) / 1e9
@@ -151,7 +167,8 @@ def workload_leg(pc, synth, torch, ctx, stream, wl, link):
     roof = roofline(best, link, d, st["kernels"][best]["ms"], max(st["kernels"][best]["launches"], 1), [st])
     del xt
     return {"n": int(n), "d": int(d), "linkage": link, "s": wall, "points_per_s": n / wall,
-            "rounds": st["rounds"], "cluster_evals": st["cluster_evals"],
+            "rounds": st["rounds"], "cluster_evals": st["cluster_evals"], "refined": st["refined"],
+            "fp64_fallbacks": st["fp64_fallbacks"],
             "point_pair_evals": st["point_pair_evals"], "cache_hits": st["cache_hits"],
             "cache_derived": st["cache_derived"], "kernels": st["kernels"], "roofline": roof}
 
@@ -171,11 +188,60 @@ PAPER_48H_S = {
 }
 
 
+def precision_leg(pc, synth, torch, ctx, stream, base):
+    """The screening tiles' element type (pc_precision) at the d = 10 and
+    d = 128 workloads: BF16 and FP32 operands beside the FP16 default (whose
+    run is in `base`); every form refines what its tiles cannot rule out in
+    FP64, so the rows must equal the FP16 form's (reported, with the largest
+    relative height difference) while the time and the number of refined
+    candidates differ."""
+    import numpy as np
+
+    from paper_2106_04727_amd import parchain
+
+    out = {}
+    dev = torch.device("cuda:0")
+    for wl, link in (("u1m_d10", "average"), ("blob100_1m_d10", "average"),
+                     ("vmf1000_200k_d128", "complete"), ("vmf1000_200k_d128", "average")):
+        key = "%s_%s" % (wl, link)
+        log("precision forms: %s, %s linkage" % (wl, link))
+        try:
+            x = synth.WORKLOADS[wl]()
+            xt = torch.from_numpy(x).to(dev)
+            w = torch.from_numpy(synth.blobs(4000, x.shape[1], 20, 0.03, 3)).to(dev)
+            row = {"fp16": {k: base[key][k] for k in ("s", "refined", "fp64_fallbacks") if k in base.get(key, {})}}
+            ref = None
+            for prec in ("fp16", "bf16", "fp32"):
+                pc.hac_device(w, link, ctx=ctx, stream=stream, precision=prec)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rows, st = pc.hac_device(xt, link, ctx=ctx, stream=stream, precision=prec)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t0
+                Z = parchain.rows_to_Z(rows)
+                if prec == "fp16":
+                    ref = Z
+                    row["fp16"].update({"s_rerun": sec, "refined": st["refined"],
+                                        "fp64_fallbacks": st["fp64_fallbacks"]})
+                    continue
+                rel = np.abs(Z[:, 2] - ref[:, 2]) / np.maximum(np.abs(ref[:, 2]), 1e-300)
+                row[prec] = {"s": sec, "refined": st["refined"], "fp64_fallbacks": st["fp64_fallbacks"],
+                             "tree_equal_fp16": bool(np.array_equal(Z[:, [0, 1, 3]], ref[:, [0, 1, 3]])),
+                             "max_rel_height_diff_vs_fp16": float(rel.max()),
+                             "median_rel_height_diff_vs_fp16": float(np.median(rel))}
+            del xt
+            out[key] = row
+        except Exception as e:  # reported, never hidden
+            out[key] = {"error": str(e)}
+    return out
+
+
 def paper_leg(pc, synth, torch, ctx, stream):
     """One run each on the paper's synthetic laws (UniformFill, GaussianDisc)
     beside the paper's 48-core time for the same set name."""
     out = {}
     for (wl, link), ref in PAPER_48H_S.items():
+        log("paper set %s, %s linkage" % (wl, link))
         try:
             r = workload_leg(pc, synth, torch, ctx, stream, wl, link)
             out["%s_%s" % (wl, link)] = {"s": r["s"], "rounds": r["rounds"], "paper_48h_s": ref,
@@ -204,6 +270,7 @@ def ablation_leg(pc, synth, torch, ctx, stream):
 
     out = {"pruning": {}, "cache": {}}
     for link in ("ward", "avgsq", "complete", "average"):
+        log("ablation: range-query pruning on / off, %s linkage" % link)
         # the unpruned search evaluates every pair: O(n^2) centroid pairs per
         # round for Ward / avg-2, O(n^2) point pairs for complete / average
         x = synth.gaussian_disc(100_000 if link in ("ward", "avgsq") else 20_000, 2, 71)
@@ -216,6 +283,7 @@ def ablation_leg(pc, synth, torch, ctx, stream):
         out["pruning"][link] = row
     x = synth.WORKLOADS["2G1M"]()
     for link in ("average", "complete"):
+        log("ablation: cache sizes, %s linkage" % link)
         row = {}
         for slots in (0, 16, 64, 256):
             sec, st = run(x, link, cache_slots=slots)
@@ -228,16 +296,17 @@ def ablation_leg(pc, synth, torch, ctx, stream):
 def serve_bench(num, slots, n_max):
     """Serving leg: a Poisson trace of clustering requests of uneven n, d and
     linkage (the serving law of ``synth.serving_trace``), first solved one at
-    a time on one context, then submitted at their arrival times to a server
-    with ``slots`` slots (open loop; the arrival rate makes the trace arrive in
-    80% of the one-at-a-time solve time, an offered load 1.25x what
-    one-at-a-time solving sustains; latency = completion - arrival, p50/p99),
-    then all at once (closed loop: throughput against one at a time)."""
+    a time on one context (the measured one-at-a-time capacity C, requests
+    per second), then submitted at their Poisson arrival times to a server
+    with ``slots`` slots at rate 0.8 C (open loop; latency = completion -
+    arrival, p50/p99), then all at once (closed loop: throughput against one
+    at a time)."""
     import numpy as np
 
     import paper_2106_04727_amd as pc
     import synth
 
+    log("serving: %d requests, one at a time first" % num)
     trace = synth.serving_trace(num, 1.0, seed=41, n_max=n_max)
     xs = [synth.request_points(r) for r in trace]
     ctx = pc.Context(0)
@@ -249,9 +318,14 @@ def serve_bench(num, slots, n_max):
             o = np.zeros((299, 4), np.int64)
             ctx.hac(w.ctypes.data, 300, d, link, o.ctypes.data, points_on_device=False, out_on_device=False)
     t0 = time.perf_counter()
-    for r, x, o in zip(trace, xs, outs):
+    alone = []
+    for i, (r, x, o) in enumerate(zip(trace, xs, outs)):
+        ta = time.perf_counter()
         ctx.hac(x.ctypes.data, r["n"], r["d"], r["linkage"], o.ctypes.data, points_on_device=False,
                 out_on_device=False)
+        alone.append(time.perf_counter() - ta)
+        if (i + 1) % 50 == 0:
+            log("serving: %d of %d solved one at a time" % (i + 1, num))
     t_seq = time.perf_counter() - t0
     ctx.close()
     # arrival rate 0.8 x the measured one-at-a-time capacity
@@ -260,6 +334,7 @@ def serve_bench(num, slots, n_max):
     scale = span / max(trace[-1]["t"], 1e-9)
     arrivals = [r["t"] * scale for r in trace]
     lat = []
+    log("serving: open loop at 0.8 x the one-at-a-time capacity (%.1f req/s)" % (num / span))
     with pc.Server(device=0, slots=slots) as srv:
         start = time.perf_counter()
         tickets = []
@@ -268,16 +343,21 @@ def serve_bench(num, slots, n_max):
             if dt > 0:
                 time.sleep(dt)
             tickets.append((srv.submit(x, r["linkage"]), time.perf_counter() - start))
-        for t, at in tickets:
+            if len(tickets) % 50 == 0:
+                log("serving: %d of %d submitted" % (len(tickets), num))
+        slow = []
+        for (t, at), ta in zip(tickets, alone):
             info = srv.wait(t)
             if info["status"] != 0:
                 raise RuntimeError("request failed: %s" % info["error"])
             lat.append(info["t_done_ms"] - info["t_submit_ms"])
+            slow.append(lat[-1] / max(1e3 * ta, 1e-3))
             srv.release(t)
         makespan = time.perf_counter() - start
         st = srv.stats()
         # closed loop: the whole trace submitted at once (throughput against
         # one-at-a-time solving of the same requests)
+        log("serving: all requests at once")
         start = time.perf_counter()
         burst = [srv.submit(x, r["linkage"]) for r, x in zip(trace, xs)]
         for t in burst:
@@ -297,6 +377,10 @@ def serve_bench(num, slots, n_max):
         "burst_speedup_vs_one_at_a_time": t_seq / burst_s,
         "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
         "latency_ms_max": float(np.max(lat)),
+        # latency over the request's own one-at-a-time time (1 = no wait, no sharing)
+        "slowdown_p50": float(np.percentile(slow, 50)), "slowdown_p99": float(np.percentile(slow, 99)),
+        "alone_ms_p50": 1e3 * float(np.percentile(alone, 50)), "alone_ms_p99": 1e3 * float(np.percentile(alone, 99)),
+        "requeued": st.get("requeued", 0),
         "peak_running": st["peak_running"], "peak_bytes_in_use": st["peak_bytes_in_use"],
         "budget_bytes": st["budget_bytes"],
     }
@@ -320,6 +404,8 @@ def main():
     ap.add_argument("--serve-nmax", type=int, default=200_000)
     ap.add_argument("--workload", default="blob50_1m_d2",
                     help="named input of synth.WORKLOADS (the headline is blob50_1m_d2)")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the BF16 / FP32 screening forms at d = 10 and 128")
     ap.add_argument("--no-ablations", action="store_true",
                     help="skip the pruning on/off and cache-size ablations")
     ap.add_argument("--copy-probe", action="store_true",
@@ -361,6 +447,7 @@ def main():
             _, st = pc.hac_device(xt, link, ctx=ctx, stream=stream, timing=True)
             collect.setdefault(link, []).append(st)
 
+    log("warm-up: %d steps of %s on %s" % (args.warmup, "+".join(links), args.workload))
     for _ in range(args.warmup):
         one_step({})
     torch.cuda.synchronize()
@@ -371,6 +458,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = 1000.0 * wall / max(args.steps, 1)
+    log("timed: %d steps, %.2f ms per step" % (args.steps, ms_step))
 
     # per-linkage summaries
     lk = {}
@@ -431,6 +519,7 @@ def main():
     }
 
     if not args.no_extra and "ward" in links:
+        log("10M-point Ward run")
         try:
             x10 = synth.blobs(10_000_000, 2, 50, 0.01, 12)
             x10t = torch.from_numpy(x10).to(dev)
@@ -448,10 +537,14 @@ def main():
         for wl, link in (("u1m_d10", "average"), ("blob100_1m_d10", "average"), ("vmf1000_200k_d128", "ward"),
                          ("vmf1000_200k_d128", "complete"), ("vmf1000_200k_d128", "average"),
                          ("vmf1000_200k_d128", "avgsq")):
+            log("workload %s, %s linkage" % (wl, link))
             try:
                 out["workloads"]["%s_%s" % (wl, link)] = workload_leg(pc, synth, torch, ctx, stream, wl, link)
             except Exception as e:  # reported, never hidden
                 out["workloads"]["%s_%s" % (wl, link)] = {"error": str(e)}
+
+    if not args.no_extra and not args.no_precision and args.workload == "blob50_1m_d2":
+        out["precision_forms"] = precision_leg(pc, synth, torch, ctx, stream, out.get("workloads", {}))
 
     if not args.no_extra and args.workload == "blob50_1m_d2":
         out["paper_sets"] = paper_leg(pc, synth, torch, ctx, stream)
@@ -475,6 +568,7 @@ def main():
         # exact queries) on the first points of the headline input itself
         cores = os.cpu_count() or 1
         m = min(args.cpu_sample, n)
+        log("CPU oracle baseline on the first %d points" % m)
         xs = np.ascontiguousarray(x[:m])
         tt, detail = 0.0, {}
         for link in links:

@@ -102,11 +102,12 @@ size_t layout(State &S, char *base, int64_t n64, int d, int linkage, bool host_p
   const bool gram = d >= kGramMinDim && d <= kGramMaxDim;
   const int kp = gram_kp(d);
   S.gkp = kp;
+  S.pkp = point_kp(d);
   S.elem = elem;
   const size_t ew = (size_t)screen_elem_bytes(elem) / 2;  // in 16-bit units
   S.g16 = c.take<_Float16>(gram ? n * kp * ew : 1);
   S.gq = c.take<float4>(gram ? n : 1);
-  S.p16 = gram && pts ? c.take<_Float16>(n * kp * ew) : nullptr;
+  S.p16 = gram && pts ? c.take<_Float16>(n * (size_t)S.pkp * ew) : nullptr;
   S.pq = c.take<float4>(gram && pts ? n : 1);
   const bool blk = gram && comp && d <= kBlkMaxDim;
   S.blk_lo = c.take<float>(blk ? (n / 64 + 2) * d : 1);

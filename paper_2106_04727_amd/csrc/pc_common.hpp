@@ -34,6 +34,15 @@ inline int gram_kp(int d) {
   if (d + 2 <= 128) return 128;
   return 144;
 }
+// MFMA depth of the point tiles of the interval screening: the dimension
+// alone (their norm terms are added outside the MFMA), in the same steps
+inline int point_kp(int d) {
+  if (d <= 16) return 16;
+  if (d <= 32) return 32;
+  if (d <= 64) return 64;
+  if (d <= 80) return 80;
+  return 128;
+}
 constexpr uint32_t kInfBits = 0x7f800000u;
 
 // element type of the MFMA screening tiles (pc_options.precision)
@@ -211,7 +220,8 @@ struct State {
   // Gram search (d >= kGramMinDim): FP16 copies of the active centroids,
   // recentred on gorg and scaled by gscale, with FP64 norms of the rounded values
   int gram;             // 1: this call searches with MFMA Gram tiles
-  int gkp;              // padded K (multiple of 16)
+  int gkp;              // padded K of the centroid tiles (multiple of 16)
+  int pkp;              // padded K of the point tiles (d rounded up to 16, 32, 64, 80, 128)
   int elem;             // ScreenElem: FP16 / BF16 / FP32 operands of the screening tiles
   _Float16 *g16;        // n x gkp elements of that type, in active-list order
   float4 *gq;  // per active item: pass-0 norm term, rigorous norm, rounding error, size/spread term

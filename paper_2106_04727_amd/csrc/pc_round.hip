@@ -2783,7 +2783,7 @@ template <int E>
 __global__ void k_pt_prep(State S) {
   typedef typename El<E>::T T;
   T *g = reinterpret_cast<T *>(S.p16);
-  const int n = S.n, d = S.d, kp = S.gkp;
+  const int n = S.n, d = S.d, kp = S.pkp;
   const double sc = *S.pscale;
   const int lane = threadIdx.x & (kWave - 1);
   const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, nw = (gridDim.x * blockDim.x) / kWave;
@@ -3749,13 +3749,12 @@ void launch_gram_refine_t(State &S, int ncand, hipStream_t s) {
     if (LINK == kComplete && S.d <= kBlkMaxDim) k_cand_seed<<<2048, kBlock, 0, s>>>(S);
     scan_exclusive_i64(S.cd_tile0, S.cd_tile0, ncand, &S.cnt->n_scr32, &S.cnt->n_ctiles, S.part, s);
     tmark(S, 1, false, s);  // the interval tiles alone
-    switch (S.gkp) {
+    switch (S.pkp) {
     case 16: launch_cand_tiles<LINK, 16>(S, ncand, s); break;
     case 32: launch_cand_tiles<LINK, 32>(S, ncand, s); break;
     case 64: launch_cand_tiles<LINK, 64>(S, ncand, s); break;
     case 80: launch_cand_tiles<LINK, 80>(S, ncand, s); break;
-    case 128: launch_cand_tiles<LINK, 128>(S, ncand, s); break;
-    default: launch_cand_tiles<LINK, 144>(S, ncand, s); break;
+    default: launch_cand_tiles<LINK, 128>(S, ncand, s); break;
     }
     tmark(S, 1, true, s);
     k_cand_bound<LINK><<<nblk(ncand, 4096), kBlock, 0, s>>>(S);

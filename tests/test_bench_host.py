@@ -20,6 +20,17 @@ def test_gram_depth_covers_d_plus_two():
     assert [bench.gram_kp(d) for d in (2, 14, 15, 30, 62, 78, 126, 127)] == [16, 16, 32, 32, 64, 80, 128, 144]
 
 
+def test_point_depth_covers_d():
+    # interval tiles: K = d padded (the norm terms are added outside the MFMA)
+    for d in range(1, 129):
+        kp = bench.point_kp(d)
+        assert kp % 16 == 0 and kp >= d
+    assert [bench.point_kp(d) for d in (10, 16, 17, 64, 65, 128)] == [16, 16, 32, 64, 80, 128]
+    st = {"kernels": {"block_search": {"visits": 1_000_000}}, "point_pair_evals": 0}
+    r = bench.roofline("block_search", "average", 128, 1.0, 1, [st])
+    assert r["bound"] == "mfma" and r["achieved"] == pytest.approx(1e6 * 2 * 128 / 1e-3 / 1e12)
+
+
 def test_visit_prices():
     # FP64 centroid + size + cluster ID; avg-2 adds its FP64 spread term,
     # complete / average the FP32 box (8d + 4 + 4 + 8d = 40 B at d = 2)
