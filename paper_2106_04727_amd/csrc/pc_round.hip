@@ -471,7 +471,7 @@ __device__ __forceinline__ double cen_key(const double *ct, double nt, double vt
 // Exact complete (largest squared distance) or average (mean distance) value
 // of a small pair, rows = the cluster with the lower ID.
 template <int LINK>
-__device__ double pair_exact_inline(const float *px, int d, int begR, int nR, int begS, int nS) {
+__device__ __forceinline__ double pair_exact_inline(const float *px, int d, int begR, int nR, int begS, int nS) {
   double acc = 0.0;
   for (int r = 0; r < nR; ++r) {
     const float *pr = px + (size_t)(begR + r) * d;
@@ -554,7 +554,7 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
 }
 
 // 0: miss, 1: hit (value in v), 2: claimed this round, value not stored yet
-__device__ int cache_find(const State &S, unsigned long long key, double &v) {
+__device__ __forceinline__ int cache_find(const State &S, unsigned long long key, double &v) {
   if (!S.cache_mask) return 0;
   const unsigned long long h = mix64(key);
   for (int i = 0; i < kCacheProbe; ++i) {
@@ -572,7 +572,7 @@ __device__ int cache_find(const State &S, unsigned long long key, double &v) {
 }
 
 // 1: claimed (caller evaluates), 2: already present, 0: no free slot
-__device__ int cache_claim(const State &S, unsigned long long key) {
+__device__ __forceinline__ int cache_claim(const State &S, unsigned long long key) {
   const unsigned long long h = mix64(key);
   for (int i = 0; i < kCacheProbe; ++i) {
     const unsigned long long idx = (h + i) & S.cache_mask;
@@ -587,7 +587,7 @@ __device__ int cache_claim(const State &S, unsigned long long key) {
 }
 
 // store a value (claimed slot or a new one); false if the probe window is full
-__device__ bool cache_fill(const State &S, unsigned long long key, double v) {
+__device__ __forceinline__ bool cache_fill(const State &S, unsigned long long key, double v) {
   const unsigned long long h = mix64(key);
   for (int i = 0; i < kCacheProbe; ++i) {
     const unsigned long long idx = (h + i) & S.cache_mask;
@@ -611,7 +611,7 @@ __device__ __forceinline__ int node_size(const State &S, int v) { return v < S.n
 // distance), average the size-weighted mean (Eq. case 2; two levels give
 // Eq. case 1). A pair being evaluated this round (pending) is not combined.
 template <int DEPTH>
-__device__ bool cache_parts(const State &S, int x, int y, double &v) {
+__device__ __forceinline__ bool cache_parts(const State &S, int x, int y, double &v) {
   const int r = cache_find(S, pair_key(x, y), v);
   if (r == 1) return true;
   if constexpr (DEPTH == 0) {
@@ -637,7 +637,7 @@ __device__ bool cache_parts(const State &S, int x, int y, double &v) {
 // combined value is stored under (x, y) when `store` (then false if it could
 // not be stored). The grid search stores nothing while it runs: its emission
 // pass treats a stored value as one its bound pass already counted.
-__device__ bool cache_resolve(const State &S, int x, int y, double &v, bool store = true) {
+__device__ __forceinline__ bool cache_resolve(const State &S, int x, int y, double &v, bool store = true) {
   if (!S.cache_mask) return false;
   const int r = cache_find(S, pair_key(x, y), v);
   if (r == 1) return true;
@@ -661,7 +661,7 @@ __device__ bool cache_resolve(const State &S, int x, int y, double &v, bool stor
 // A pair whose value combines from cached parts is not evaluated: it joins
 // the list of pairs whose values are read back from the cache.
 // Its value travels with the entry and is stored after the search.
-__device__ bool pend_if_resolved(const State &S, int ti, int c) {
+__device__ __forceinline__ bool pend_if_resolved(const State &S, int ti, int c) {
   double v;
   if (!cache_resolve(S, S.node[S.term[ti]], S.node[c], v, false)) return false;
   const long long q = append_slot(&S.cnt->n_pend);
