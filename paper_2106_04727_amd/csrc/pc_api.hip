@@ -363,12 +363,17 @@ size_t pc_hac_workspace_bytes(int64_t n, int32_t d, int32_t linkage, const pc_op
 // call fails with PC_ERR_OUT_OF_MEMORY instead of growing without bound.
 constexpr long long kMaxRecord = 1LL << 30;
 
-// Scan partials: one per 1024 elements of the longest scan of the call.
+// Scan workspace: two status words per 1024 elements of the longest scan of
+// the call (two arrays taken in turn), plus the tickets.
 static pc_status grow_part(pc_context *ctx, State &S, long long longest_scan) {
-  const long long need = longest_scan / 1024 + 1024;
+  const long long need = 2 * (longest_scan / 1024 + 1024) + 1;
+  void *old = ctx->cur->part.p;
   HIPCHK(grow(ctx, ctx->cur->part, (size_t)need * sizeof(long long)));
   S.part = (long long *)ctx->cur->part.p;
   S.part_cap = (long long)(ctx->cur->part.bytes / sizeof(long long));
+  // new memory (or a first use in this call) holds stale status words
+  if (ctx->cur->part.p != old || S.sws.st[0] != (unsigned long long *)S.part)
+    scan_ws_carve(S.sws, S.part, S.part_cap, &S.cnt->scan_err);
   return PC_OK;
 }
 
@@ -377,7 +382,7 @@ static pc_status grow_part(pc_context *ctx, State &S, long long longest_scan) {
 constexpr size_t kPairBytes = 4 * sizeof(long long) + 6 * sizeof(int);
 // per candidate: lower bound, value, screening bound (f64), tile prefix
 // (i64), point ranges (int4), terminal, cluster, small-list entry (i32)
-constexpr size_t kCandBytes = 3 * sizeof(double) + sizeof(long long) + sizeof(int4) + 4 * sizeof(int);
+constexpr size_t kCandBytes = 3 * sizeof(double) + sizeof(long long) + sizeof(int4) + 8 + 4 * sizeof(int);
 
 static pc_status grow_pairs(pc_context *ctx, State &S, long long cap) {
   if (cap > kMaxRecord) return fail(PC_ERR_OUT_OF_MEMORY, "a round needs more than 2^30 cluster pairs");
@@ -425,7 +430,8 @@ static pc_status grow_cand(pc_context *ctx, State &S, long long cap) {
   S.cd_l0 = S.cd_v + cc;
   S.cd_tile0 = (long long *)(S.cd_l0 + cc);  // 32 cc bytes in: the int4 records stay 16-byte aligned
   S.cd_desc = (int4 *)(S.cd_tile0 + cc);
-  S.cd_t = (int *)(S.cd_desc + cc);
+  S.cd_x = (unsigned long long *)(S.cd_desc + cc);
+  S.cd_t = (int *)(S.cd_x + cc);
   S.cd_c = S.cd_t + cc;
   S.cd_small = S.cd_c + cc;
   S.cd_scr = S.cd_small + cc;
@@ -453,7 +459,7 @@ static pc_status carve_scratch(char *base, size_t ws, int64_t n, int d, int link
   // scan partials for the longest scan a record of this scratch can need
   const size_t left = total - off;
   const long long longest = std::max<long long>(2 * n + 64, (long long)(left / kPairBytes) + 1);
-  take(B.part, (size_t)(longest / 1024 + 1024) * sizeof(long long));
+  take(B.part, (size_t)(2 * (longest / 1024 + 1024) + 1) * sizeof(long long));
   if (off + (1u << 20) > total)
     return fail(PC_ERR_OUT_OF_MEMORY, "input too large for the allocation-free scratch buffer");
   const size_t rest = total - off - 8 * 256;  // alignment slack of the windows below
@@ -876,6 +882,7 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
     if (h.nonfinite == 2) return fail(PC_ERR_DEVICE, "a terminal found no neighbour");
     if (h.nonfinite == 3) return fail(PC_ERR_DEVICE, "internal index check failed");
     if (h.nonfinite == 4) return fail(PC_ERR_DEVICE, "a claimed cache entry was never filled");
+    if (h.scan_err) return fail(PC_ERR_DEVICE, "a prefix scan's look-back gave up");
     if (S.cache_mask && h.cache_inserts - cache_base > (long long)(S.cache_mask + 1) / 2) {
       // rebuild: keep only entries whose two clusters are still alive
       const int nxt = 1 - cache_cur;

@@ -44,6 +44,11 @@ inline int point_kp(int d) {
   return 128;
 }
 constexpr uint32_t kInfBits = 0x7f800000u;
+// complete linkage: the interval tiles settled no exact key for this candidate
+constexpr unsigned long long kNoExact = ~0ull;
+// complete linkage above these point depths: exact keys of the pairs that may
+// be the farthest are taken inside the interval tiles (see k_cand_tiles)
+__host__ __device__ inline bool tiles_settle_complete(int pkp, int d) { return !(pkp <= 32 && d <= kBlkMaxDim); }
 
 // element type of the MFMA screening tiles (pc_options.precision)
 enum ScreenElem { kElF16 = 0, kElBF16 = 1, kElF32 = 2 };
@@ -133,8 +138,22 @@ struct Counters {
   long long n_ctiles;  // interval tiles of the current batch
   long long n_small;   // small candidates of the current batch
   long long n_scr;     // screened candidates of the current batch
-  int n_scr32, pad_scr;
+  int n_scr32;
+  int scan_err;        // a prefix scan's look-back gave up (see ScanWs)
   long long refined;   // screened candidates given an exact FP64 value
+};
+
+// Workspace of the single-pass prefix scans (decoupled look-back): two status
+// arrays taken in turn, each scan clearing the other one for the next scan
+// (launches on one stream run in order), their two block tickets, and the
+// error flag a look-back raises if it gives up (it never hangs).
+struct ScanWs {
+  unsigned long long *st[2];
+  int *ticket;  // two ints, one per status array
+  int cap;      // status words per array (one per 1024 scanned elements)
+  int turn;     // host: the array the next scan uses
+  int fresh;    // host: the arrays hold stale words (new memory): clear first
+  int *err;     // device: Counters::scan_err
 };
 
 // All device arrays of one clustering call. Slots are storage indices of
@@ -193,8 +212,9 @@ struct State {
   unsigned long long *sk0, *sk1;
   unsigned *sv0, *sv1;
   int *hist;
-  long long *part;  // scan partials (growable with the pair list)
+  long long *part;  // scan workspace (growable with the pair list)
   long long part_cap;
+  ScanWs sws;
   GridParams *grid;
   Counters *cnt;
   // deferred pair evaluations (growable, owned by the context)
@@ -236,6 +256,8 @@ struct State {
   int4 *cd_desc;  // screened candidates (dense): row begin, rows, column begin, columns
   int *cd_scr;    // screened candidates (dense): candidate index
   double *cd_l0;  // screened candidates (dense), complete: a lower bound of the key fixed before the tiles
+  unsigned long long *cd_x;  // screened candidates (dense), complete: bits of the largest exact point-pair key
+                            // found by the tiles (kNoExact: the tiles did not settle the key)
   float *blk_lo, *blk_hi;  // complete, d <= kBlkMaxDim: box of each 64-position block of points (d each)
   int *nparent;  // node -> parent node (-1: none yet); kept when the cache is on
   double *gorg;         // d
@@ -268,13 +290,15 @@ struct State {
 
 // ------------------------------------------------------ launch wrappers ----
 // primitives (pc_prims.hip)
-void scan_exclusive_i32(const int *in, int *out, int nmax, const int *dlen, int *dtotal,
-                        long long *part, hipStream_t s);
+// the scan workspace over `words` long longs at `base`
+void scan_ws_carve(ScanWs &ws, long long *base, long long words, int *err);
+void scan_exclusive_i32(const int *in, int *out, int nmax, const int *dlen, int *dtotal, ScanWs &ws,
+                        hipStream_t s);
 void scan_exclusive_i64(const long long *in, long long *out, int nmax, const int *dlen,
-                        long long *dtotal, long long *part, hipStream_t s);
+                        long long *dtotal, ScanWs &ws, hipStream_t s);
 // stable radix sort of (key, value) pairs by the low `bits` bits of key
 void radix_sort_pairs(unsigned long long *&k0, unsigned long long *&k1, unsigned *&v0,
-                      unsigned *&v1, int n, int bits, int *hist, long long *part, hipStream_t s);
+                      unsigned *&v1, int n, int bits, int *hist, ScanWs &ws, hipStream_t s);
 int radix_hist_len(int n);
 
 // round kernels (pc_round.hip)

@@ -48,72 +48,101 @@ __device__ __forceinline__ int scan_len(int nmax, const int *dlen) {
   return l < nmax ? l : nmax;
 }
 
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const T *in, int nmax, const int *dlen,
-                                                        long long *part) {
-  const int len = scan_len<T>(nmax, dlen);
-  const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  T s = 0;
-#pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    long long i = base + j;
-    if (i < len) s += in[i];
-  }
-  T tot;
-  block_exclusive_scan<T>(s, tot);
-  if (threadIdx.x == 0) part[blockIdx.x] = (long long)tot;
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_partials(long long *part, int nb, long long *total64,
-                                                          int *total32) {
-  long long carry = 0;
-  for (int b0 = 0; b0 < nb; b0 += kScanTile) {
-    long long v[kScanItems];
-    long long s = 0;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-      int i = b0 + threadIdx.x * kScanItems + j;
-      v[j] = (i < nb) ? part[i] : 0;
-      s += v[j];
-    }
-    long long tot;
-    long long ex = block_exclusive_scan<long long>(s, tot);
-    long long run = carry + ex;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-      int i = b0 + threadIdx.x * kScanItems + j;
-      if (i < nb) part[i] = run;
-      run += v[j];
-    }
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    if (total64) *total64 = carry;
-    if (total32) *total32 = (int)carry;
-  }
-}
+// Single-pass exclusive scan by decoupled look-back. A block takes the next
+// ticket (so every block it waits for has started), scans its 1024 items,
+// publishes its total (flag 1), adds the totals of the blocks before it until
+// it meets a published prefix (flag 2), and publishes its own prefix. One
+// wavefront looks back 64 blocks at a time. The status array of the next
+// scan is cleared on the way. A look-back that waits beyond kSpinLimit
+// windows gives up with the part it has (every output position then stays
+// at or below its true value) and raises the error flag.
+constexpr unsigned long long kStValue = (1ull << 62) - 1;
+constexpr int kSpinLimit = 1 << 22;
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_scan_down(const T *in, T *out, int nmax, const int *dlen,
-                                                      const long long *part) {
+__global__ __launch_bounds__(kBlock) void k_scan_lb(const T *in, T *out, int nmax, const int *dlen,
+                                                    unsigned long long *st, int *ticket,
+                                                    unsigned long long *st_next, int *ticket_next, int cap,
+                                                    long long *total64, int *total32, int *err) {
+  __shared__ int sbid;
+  __shared__ T sprefix;
+  if (threadIdx.x == 0) sbid = atomicAdd(ticket, 1);
+  __syncthreads();
+  const int bid = sbid;
+  for (int j = bid * kBlock + threadIdx.x; j < cap; j += gridDim.x * kBlock) st_next[j] = 0ull;
+  if (bid == 0 && threadIdx.x == 0) *ticket_next = 0;
   const int len = scan_len<T>(nmax, dlen);
-  const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  const long long base = (long long)bid * kScanTile + threadIdx.x * kScanItems;
   T v[kScanItems];
   T s = 0;
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
-    long long i = base + j;
-    v[j] = (i < len) ? in[i] : (T)0;
+    const long long i = base + j;
+    v[j] = i < len ? in[i] : (T)0;
     s += v[j];
   }
   T tot;
-  T run = block_exclusive_scan<T>(s, tot) + (T)part[blockIdx.x];
+  const T ex = block_exclusive_scan<T>(s, tot);
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    T prefix = 0;
+    if (bid == 0) {
+      if (lane == 0)
+        __hip_atomic_store(&st[0], (2ull << 62) | (unsigned long long)tot, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      if (lane == 0)
+        __hip_atomic_store(&st[bid], (1ull << 62) | (unsigned long long)tot, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      int top = bid - 1;  // the nearest block not yet added
+      int spins = 0;
+      while (true) {
+        const int idx = top - lane;
+        const unsigned long long w =
+            idx >= 0 ? __hip_atomic_load(&st[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : (2ull << 62);
+        const unsigned long long pm = __ballot((w >> 62) == 2ull);
+        const int fp = pm ? __ffsll((long long)pm) - 1 : kWave;  // nearest published prefix
+        const unsigned long long need = fp >= kWave - 1 ? ~0ull : ((2ull << fp) - 1ull);
+        if (__ballot((w >> 62) == 0ull) & need) {
+          // a block in the window has not published yet
+          if (++spins > kSpinLimit) {
+            if (lane == 0) atomicExch(err, 1);
+            break;
+          }
+          continue;
+        }
+        T add = lane <= fp ? (T)(w & kStValue) : (T)0;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) add += __shfl_xor(add, o, kWave);
+        prefix += add;
+        if (fp < kWave) break;
+        top -= kWave;
+      }
+      if (lane == 0)
+        __hip_atomic_store(&st[bid], (2ull << 62) | (unsigned long long)(prefix + tot), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane == 0) {
+      sprefix = prefix;
+      if (bid == (int)gridDim.x - 1) {
+        if (total64) *total64 = (long long)(prefix + tot);
+        if (total32) *total32 = (int)(prefix + tot);
+      }
+    }
+  }
+  __syncthreads();
+  T run = ex + sprefix;
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
-    long long i = base + j;
+    const long long i = base + j;
     if (i < len) out[i] = run;
     run += v[j];
   }
+}
+
+__global__ void k_zero_words(unsigned long long *p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0ull;
 }
 
 // ------------------------------------------------------------ radix sort --
@@ -220,47 +249,68 @@ __global__ __launch_bounds__(kBlock) void k_scan_single(const T *in, T *out, int
 
 }  // namespace
 
-void scan_exclusive_i32(const int *in, int *out, int nmax, const int *dlen, int *dtotal,
-                        long long *part, hipStream_t s) {
+void scan_ws_carve(ScanWs &ws, long long *base, long long words, int *err) {
+  ws.cap = (int)std::min<long long>((words - 1) / 2, 0x7fffffffLL);
+  ws.st[0] = (unsigned long long *)base;
+  ws.st[1] = ws.st[0] + ws.cap;
+  ws.ticket = (int *)(ws.st[1] + ws.cap);
+  ws.turn = 0;
+  ws.fresh = 1;
+  ws.err = err;
+}
+
+// Launches one scan: a single block for short ones, else the look-back scan.
+template <class T>
+static void scan_exclusive(const T *in, T *out, int nmax, const int *dlen, long long *dtotal64, int *dtotal32,
+                           ScanWs &ws, hipStream_t s) {
+  if (nmax <= kSingleScan) {
+    k_scan_single<T><<<1, kBlock, 0, s>>>(in, out, nmax, dlen, dtotal64, dtotal32);
+    return;
+  }
+  if (ws.fresh) {
+    // both status arrays and the tickets start at zero
+    k_zero_words<<<64, kBlock, 0, s>>>(ws.st[0], 2LL * ws.cap + 1);
+    ws.fresh = 0;
+  }
+  const int nb = blocks_for(nmax, kScanTile);
+  if (nb > ws.cap) {
+    // (the workspace is sized for the longest scan; one block is slow but safe)
+    k_scan_single<T><<<1, kBlock, 0, s>>>(in, out, nmax, dlen, dtotal64, dtotal32);
+    return;
+  }
+  const int a = ws.turn;
+  ws.turn ^= 1;
+  k_scan_lb<T><<<nb, kBlock, 0, s>>>(in, out, nmax, dlen, ws.st[a], ws.ticket + a, ws.st[a ^ 1],
+                                     ws.ticket + (a ^ 1), ws.cap, dtotal64, dtotal32, ws.err);
+}
+
+void scan_exclusive_i32(const int *in, int *out, int nmax, const int *dlen, int *dtotal, ScanWs &ws,
+                        hipStream_t s) {
   if (nmax <= 0) {
     if (dtotal) hipMemsetAsync(dtotal, 0, sizeof(int), s);
     return;
   }
-  if (nmax <= kSingleScan) {
-    k_scan_single<int><<<1, kBlock, 0, s>>>(in, out, nmax, dlen, nullptr, dtotal);
-    return;
-  }
-  const int nb = blocks_for(nmax, kScanTile);
-  k_scan_reduce<int><<<nb, kBlock, 0, s>>>(in, nmax, dlen, part);
-  k_scan_partials<<<1, kBlock, 0, s>>>(part, nb, nullptr, dtotal);
-  k_scan_down<int><<<nb, kBlock, 0, s>>>(in, out, nmax, dlen, part);
+  scan_exclusive<int>(in, out, nmax, dlen, nullptr, dtotal, ws, s);
 }
 
 void scan_exclusive_i64(const long long *in, long long *out, int nmax, const int *dlen,
-                        long long *dtotal, long long *part, hipStream_t s) {
+                        long long *dtotal, ScanWs &ws, hipStream_t s) {
   if (nmax <= 0) {
     if (dtotal) hipMemsetAsync(dtotal, 0, sizeof(long long), s);
     return;
   }
-  if (nmax <= kSingleScan) {
-    k_scan_single<long long><<<1, kBlock, 0, s>>>(in, out, nmax, dlen, dtotal, nullptr);
-    return;
-  }
-  const int nb = blocks_for(nmax, kScanTile);
-  k_scan_reduce<long long><<<nb, kBlock, 0, s>>>(in, nmax, dlen, part);
-  k_scan_partials<<<1, kBlock, 0, s>>>(part, nb, dtotal, nullptr);
-  k_scan_down<long long><<<nb, kBlock, 0, s>>>(in, out, nmax, dlen, part);
+  scan_exclusive<long long>(in, out, nmax, dlen, dtotal, nullptr, ws, s);
 }
 
 int radix_hist_len(int n) { return 256 * blocks_for(n > 0 ? n : 1, kSortTile); }
 
 void radix_sort_pairs(unsigned long long *&k0, unsigned long long *&k1, unsigned *&v0, unsigned *&v1,
-                      int n, int bits, int *hist, long long *part, hipStream_t s) {
+                      int n, int bits, int *hist, ScanWs &ws, hipStream_t s) {
   if (n <= 1) return;
   const int nb = blocks_for(n, kSortTile);
   for (int shift = 0; shift < bits; shift += 8) {
     k_radix_hist<<<nb, kBlock, 0, s>>>(k0, n, shift, hist, nb);
-    scan_exclusive_i32(hist, hist, 256 * nb, nullptr, nullptr, part, s);
+    scan_exclusive_i32(hist, hist, 256 * nb, nullptr, nullptr, ws, s);
     k_radix_scatter<<<nb, kBlock, 0, s>>>(k0, v0, k1, v1, n, shift, hist, nb);
     unsigned long long *tk = k0;
     k0 = k1;

@@ -2865,7 +2865,10 @@ __global__ void k_cand_triage(State S, int ncand) {
     if (cost <= kInlinePairs) {
       const long long k = append_slot(&S.cnt->n_small);
       S.cd_small[k] = i;  // k < ncand: every candidate appends at most once
-    } else if (d >= (LINK == kComplete ? kGramMinDim : kIntervalMinDim) && cost * d >= kIntervalWork) {
+    } else if (d >= (LINK == kComplete ? kGramMinDim : kIntervalMinDim) &&
+               (cost * d >= kIntervalWork || (LINK == kComplete && tiles_settle_complete(S.pkp, d)))) {
+      // (complete, settled in the tiles: every candidate above the inline
+      // size, the tiles being far cheaper than FP64 tiles of padded pairs)
       // dense list of screened candidates: tile count, point ranges, index
       const long long k = append_slot(&S.cnt->n_scr);
       S.cd_tile0[k] = (long long)((nt + kGT - 1) / kGT) * ((nc + kGT - 1) / kGT);
@@ -2885,6 +2888,7 @@ __global__ void k_cand_triage(State S, int ncand) {
         l0 = lb > 0.0 ? lb * (1.0 - 1e-9) : 0.0;
       }
       S.cd_l0[k] = l0;
+      S.cd_x[k] = LINK == kComplete && tiles_settle_complete(S.pkp, d) ? 0ull : kNoExact;
       S.cd_lb[i] = l0;
       S.cd_v[i] = 0.0;
     }
@@ -3016,12 +3020,68 @@ __global__ void k_cand_small(State S) {
   count_add(&S.cnt->point_pairs, ppairs);
 }
 
+// Squared distance of points a and b in FP64, coordinates summed in order
+// (the complete-linkage key of a point pair); 16-byte reads when d is a
+// multiple of 4.
+__device__ __forceinline__ double pair_sq_exact(const float *px, int a, int b, int d) {
+  const float *x = px + (size_t)a * d, *y = px + (size_t)b * d;
+  double q = 0.0;
+  if ((d & 3) == 0) {
+    for (int k = 0; k < d; k += 4) {
+      const float4 u4 = *(const float4 *)(x + k), v4 = *(const float4 *)(y + k);
+      double u = (double)u4.x - (double)v4.x;
+      q += u * u;
+      u = (double)u4.y - (double)v4.y;
+      q += u * u;
+      u = (double)u4.z - (double)v4.z;
+      q += u * u;
+      u = (double)u4.w - (double)v4.w;
+      q += u * u;
+    }
+  } else {
+    for (int k = 0; k < d; ++k) {
+      const double u = (double)x[k] - (double)y[k];
+      q += u * u;
+    }
+  }
+  return q;
+}
+
+// Position of the r-th set bit (from 0) of m, which has more than r set bits.
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int r) {
+  int base = 0;
+#pragma unroll
+  for (int w = 32; w > 0; w >>= 1) {
+    const unsigned long long low = m & ((1ull << w) - 1);
+    const int c = __popcll(low);
+    if (r >= c) {
+      r -= c;
+      m >>= w;
+      base += w;
+    } else {
+      m = low;
+    }
+  }
+  return base;
+}
+
+// exact point-pair keys a wavefront takes per tile before it leaves the
+// candidate to the exact pass instead
+constexpr int kSettleCap = 4 * kWave;
+
 // One block per 64x64 tile of a screened candidate's point pairs (rows: the
 // terminal's points), four 32x32 MFMA sub-tiles; the tile's bound
 // contributions are added (average) or maxed (complete) into the candidate.
 // Each block walks a contiguous range of tiles; the next tile's points are
 // loaded into registers while the current one is computed.
-template <int LINK, int KP, int EL>
+// SETTLE (complete): the same tiles again, for the candidates that survived
+// their terminal's bound only (cd_l0 >= 0: sqrt(L) in tile units, L the
+// candidate's final lower bound). A pair whose upper bound reaches L gets its
+// exact FP64 key, the largest of which is the candidate's key: the farthest
+// pair's upper bound reaches L. A wavefront that meets more than kSettleCap
+// such pairs in one tile (near-equal distances) leaves the candidate to the
+// exact pass instead (cd_x = kNoExact).
+template <int LINK, int KP, int EL, bool SETTLE>
 __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
   typedef typename El<EL>::T T;
   constexpr int KS = El<EL>::KS;
@@ -3037,7 +3097,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const double isc = 1.0 / *S.pscale;
-  long long pairs = 0;
+  long long pairs = 0, settled = 0;
   const int nscr = S.cnt->n_scr32;
   long long ta, te;
   tile_share(ntiles, ta, te);
@@ -3065,13 +3125,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
   ahead();
   uint4 reg[NCH];
   float4 rq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  int cur_i = 0, cur_nr = 0, cur_nc = 0;
+  int cur_i = 0, cur_nr = 0, cur_nc = 0, cur_k = 0, cur_ba = 0, cur_bb = 0;
   // complete, d <= kBlkMaxDim: a tile whose block boxes cannot reach the
   // candidate's fixed lower bound holds no farthest pair and is skipped (the
   // tile holding the farthest pair always reaches it, so L and H stay valid);
   // the decision uses values no thread writes during the kernel, so it is
   // uniform over the block
-  const bool prune = LINK == kComplete && KP <= 32 && S.d <= kBlkMaxDim;  // compiled out above K = 32
+  const bool prune = !SETTLE && LINK == kComplete && KP <= 32 && S.d <= kBlkMaxDim;  // compiled out above K = 32
+  static_assert(!SETTLE || LINK == kComplete, "settling takes complete linkage's maximum");
   int ba = 0, bb = 0, nr = 0, nc = 0;
   auto locate = [&](long long tile) {
     if (tile >= oend) {
@@ -3108,6 +3169,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
     cur_i = oi;
     cur_nr = nr;
     cur_nc = nc;
+    cur_k = own;
+    cur_ba = ba;
+    cur_bb = bb;
   };
   // the first tile at or after `tile` that is not skipped (its points
   // loaded), or te. The bound is the entry's fixed L0, raised for the entry
@@ -3123,6 +3187,18 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
   if (threadIdx.x == 0) snap_own = -1;
   __syncthreads();
   auto next_tile = [&](long long tile) -> long long {
+    if (SETTLE) {
+      // the rest of an entry that did not survive is skipped
+      while (tile < te) {
+        locate(tile);
+        if (S.cd_l0[own] >= 0.0) {
+          fetch(tile);
+          return tile;
+        }
+        tile = oend;
+      }
+      return te;
+    }
     if (!prune) {
       if (tile < te) fetch(tile);
       return tile < te ? tile : te;
@@ -3157,7 +3233,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
   };
   long long tile = next_tile(ta);
   while (tile < te) {
-    const int i = cur_i, nr = cur_nr, ncl = cur_nc;
+    const int i = cur_i, nr = cur_nr, ncl = cur_nc, kc = cur_k, ta0 = cur_ba, tb0 = cur_bb;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NCH; ++u) {
@@ -3241,6 +3317,69 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
       eps += __shfl_xor(eps, o, kWave);
       mx = fmaxf(mx, __shfl_xor(mx, o, kWave));
     }
+    if (SETTLE && mx > -INFINITY) {
+      // per pair: exact key <= ((sqrt(d2 + E) (1 + 1e-6) + em) isc)^2, the
+      // tile's bracket applied to one pair. Pairs with d2 below T cannot
+      // reach L (T lowered for its own roundings).
+      const double E = (double)side[0][2] + (double)side[1][2];
+      const double em = (double)side[0][1] + (double)side[1][1];
+      const double a = S.cd_l0[kc] - em;
+      float T = -INFINITY;
+      if (a > 0.0) {
+        double t2 = a * a - E;
+        t2 -= fabs(t2) * 1e-6 + a * a * 1e-6;
+        T = (float)t2;
+      }
+      if (mx >= T) {
+        // the ballot of accumulator k: which lanes' pair k qualifies
+        auto qual = [&](int k) -> unsigned long long {
+          const int row = wr + (k >> 2) * 8 + (lane >> 5) * 4 + (k & 3);
+          const float d2 = __builtin_fmaf(-2.0f, acc[k], an[0][row] + cn);
+          return __ballot(cval && row < nr && d2 >= T);
+        };
+        int tot = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tot += __popcll(qual(k));
+        if (tot > kSettleCap) {
+          if (lane == 0) atomicMax(&S.cd_x[kc], kNoExact);
+        } else if (tot > 0) {
+          // lane j takes the j-th qualifying pair (k-major, then lane order)
+          double best = -1.0;
+          for (int j0 = 0; j0 < tot; j0 += kWave) {
+            const int j = j0 + lane;
+            int rem = j, ks = -1;
+            unsigned long long m = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+              const unsigned long long b = qual(k);
+              const int c = __popcll(b);
+              if (ks < 0) {
+                if (rem < c) {
+                  ks = k;
+                  m = b;
+                } else {
+                  rem -= c;
+                }
+              }
+            }
+            if (j >= tot) continue;
+            const int src = nth_set_bit(m, rem);
+            const int row = wr + (ks >> 2) * 8 + (src >> 5) * 4 + (ks & 3);
+            const int cl = wc + (src & 31);
+            best = fmax(best, pair_sq_exact(S.px, ta0 + row, tb0 + cl, S.d));
+          }
+          best = wave_max(best);
+          if (lane == 0) {
+            atomicMax(&S.cd_x[kc], pos_bits(best));
+            settled += tot;
+          }
+        }
+      }
+    }
+    if (SETTLE) {
+      tile = nxt;
+      continue;
+    }
     if (lane == 0) {
       red[0][w] = sum;
       red[1][w] = eps;
@@ -3273,7 +3412,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
     }
     tile = nxt;
   }
-  count_add(&S.cnt->visits[1], pairs);  // nonzero in thread 0 only
+  if (SETTLE)
+    count_add(&S.cnt->point_pairs, settled);
+  else
+    count_add(&S.cnt->visits[1], pairs);  // nonzero in thread 0 only
 }
 
 // Screened candidates: L kept as the candidate's lower bound, H lowers the
@@ -3295,6 +3437,34 @@ __global__ void k_cand_bound(State S) {
     }
     S.cd_lb[i] = l;
     atomicMin((unsigned long long *)&S.t_beta[ti], pos_bits(h));
+  }
+}
+
+// Complete, settled in the tiles: the screened candidates that survive their
+// terminal's final bound (the test of k_gram_exact) get sqrt(L) in tile units
+// (the threshold of the SETTLE tile pass); the others -1.
+__global__ void k_settle_select(State S) {
+  const int nscr = S.cnt->n_scr32;
+  const double sc = *S.pscale;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nscr; k += gridDim.x * blockDim.x) {
+    const int i = S.cd_scr[k];
+    const double l = S.cd_lb[i];
+    S.cd_l0[k] = l <= S.t_beta[S.cd_t[i]] * kSlack ? sqrt(l) * sc / (1.0 + 1e-6) : -1.0;
+  }
+}
+
+// Settled survivors: the largest exact pair key is the candidate's value (an
+// exact value, like a small pair's); a survivor the tiles could not settle
+// keeps its lower bound and goes to the exact pass.
+__global__ void k_settle_finish(State S) {
+  const int nscr = S.cnt->n_scr32;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nscr; k += gridDim.x * blockDim.x) {
+    if (!(S.cd_l0[k] >= 0.0)) continue;
+    const unsigned long long x = S.cd_x[k];
+    const int i = S.cd_scr[k];
+    if (x == kNoExact || (x == 0ull && S.cd_lb[i] > 0.0)) continue;
+    S.cd_lb[i] = -1.0;
+    S.cd_v[i] = pos_from_bits(x);
   }
 }
 
@@ -3728,12 +3898,12 @@ void launch_gram_kp(State &S, int nact, hipStream_t s) {
   }
 }
 
-template <int LINK, int KP>
+template <int LINK, int KP, bool SETTLE>
 void launch_cand_tiles(State &S, int ncand, hipStream_t s) {
   switch (S.elem) {
-  case kElBF16: k_cand_tiles<LINK, KP, kElBF16><<<8192, kBlock, 0, s>>>(S, ncand); break;
-  case kElF32: k_cand_tiles<LINK, KP, kElF32><<<8192, kBlock, 0, s>>>(S, ncand); break;
-  default: k_cand_tiles<LINK, KP, kElF16><<<8192, kBlock, 0, s>>>(S, ncand); break;
+  case kElBF16: k_cand_tiles<LINK, KP, kElBF16, SETTLE><<<8192, kBlock, 0, s>>>(S, ncand); break;
+  case kElF32: k_cand_tiles<LINK, KP, kElF32, SETTLE><<<8192, kBlock, 0, s>>>(S, ncand); break;
+  default: k_cand_tiles<LINK, KP, kElF16, SETTLE><<<8192, kBlock, 0, s>>>(S, ncand); break;
   }
 }
 
@@ -3747,17 +3917,31 @@ void launch_gram_refine_t(State &S, int ncand, hipStream_t s) {
     k_cand_small<LINK><<<8192, kBlock, 0, s>>>(S);
     k_scr_count<<<1, 1, 0, s>>>(S.cnt);
     if (LINK == kComplete && S.d <= kBlkMaxDim) k_cand_seed<<<2048, kBlock, 0, s>>>(S);
-    scan_exclusive_i64(S.cd_tile0, S.cd_tile0, ncand, &S.cnt->n_scr32, &S.cnt->n_ctiles, S.part, s);
+    scan_exclusive_i64(S.cd_tile0, S.cd_tile0, ncand, &S.cnt->n_scr32, &S.cnt->n_ctiles, S.sws, s);
     tmark(S, 1, false, s);  // the interval tiles alone
     switch (S.pkp) {
-    case 16: launch_cand_tiles<LINK, 16>(S, ncand, s); break;
-    case 32: launch_cand_tiles<LINK, 32>(S, ncand, s); break;
-    case 64: launch_cand_tiles<LINK, 64>(S, ncand, s); break;
-    case 80: launch_cand_tiles<LINK, 80>(S, ncand, s); break;
-    default: launch_cand_tiles<LINK, 128>(S, ncand, s); break;
+    case 16: launch_cand_tiles<LINK, 16, false>(S, ncand, s); break;
+    case 32: launch_cand_tiles<LINK, 32, false>(S, ncand, s); break;
+    case 64: launch_cand_tiles<LINK, 64, false>(S, ncand, s); break;
+    case 80: launch_cand_tiles<LINK, 80, false>(S, ncand, s); break;
+    default: launch_cand_tiles<LINK, 128, false>(S, ncand, s); break;
     }
     tmark(S, 1, true, s);
     k_cand_bound<LINK><<<nblk(ncand, 4096), kBlock, 0, s>>>(S);
+    if (LINK == kComplete && tiles_settle_complete(S.pkp, S.d)) {
+      // the survivors' tiles again: exact keys of the pairs that may be the
+      // farthest (counted with the exact pair tiles)
+      k_settle_select<<<nblk(ncand, 4096), kBlock, 0, s>>>(S);
+      tmark(S, 2, false, s);
+      switch (S.pkp) {
+      case 32: launch_cand_tiles<kComplete, 32, true>(S, ncand, s); break;
+      case 64: launch_cand_tiles<kComplete, 64, true>(S, ncand, s); break;
+      case 80: launch_cand_tiles<kComplete, 80, true>(S, ncand, s); break;
+      default: launch_cand_tiles<kComplete, 128, true>(S, ncand, s); break;
+      }
+      tmark(S, 2, true, s);
+      k_settle_finish<<<nblk(ncand, 4096), kBlock, 0, s>>>(S);
+    }
   }
 exact:
   tmark(S, 3, false, s);
@@ -3862,7 +4046,7 @@ void launch_init(State &S, const float *x, hipStream_t s) {
   k_reset_round<<<1, 1, 0, s>>>(S.cnt);
   k_point_bbox<<<nblk(n, 1024), kBlock, 0, s>>>(x, n, S.d, axes, S.cnt);
   k_morton<<<nblk(n, 1 << 22), kBlock, 0, s>>>(x, n, S.d, axes, S.cnt, S.sk0, S.sv0);
-  radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, n, key_bits, S.hist, S.part, s);
+  radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, n, key_bits, S.hist, S.sws, s);
   k_init_slots<<<nblk(n, 1 << 22), kBlock, 0, s>>>(S, x, S.sv0);
   k_set_nact<<<1, 1, 0, s>>>(S.cnt, n);
   if (S.p16) {
@@ -3880,7 +4064,7 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
   S.single = 0;
   k_reset_round<<<1, 1, 0, s>>>(S.cnt);
   k_act_pass<<<gb, kBlock, 0, s>>>(S, round);
-  scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, &S.cnt->n_term, S.part, s);
+  scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, &S.cnt->n_term, S.sws, s);
   k_scatter_flagged<<<gb, kBlock, 0, s>>>(S.act, S.flags, S.scan, &S.cnt->n_act, S.term);
   // Few active clusters: a block per terminal scans all of them (every
   // candidate's bounds and values are those of the ring search, so the rows
@@ -3894,7 +4078,7 @@ void launch_round(State &S, int round, int nact, hipStream_t s, bool &need_pairs
     k_cell_count<<<gb, kBlock, 0, s>>>(S);
     // cells <= cell_cap; scan length ncell + 1 (the extra zero gives the total)
     scan_exclusive_i32(S.cell_cnt, S.cell_start, grid_cells_max(S.cell_cap, nact) + 1, &S.grid->ncell1, nullptr,
-                       S.part, s);
+                       S.sws, s);
     k_cell_scatter<<<gb, kBlock, 0, s>>>(S);
   }
   int *t_ovf = S.cell_rank;  // per-terminal hand-off flags (cell ranks are no longer needed)
@@ -3971,10 +4155,10 @@ void launch_pairs_prefix(State &S, int npairs, hipStream_t s) {
   long long *tmp = S.pr_tile0;  // per-pair counts, then their exclusive prefix (in place)
   if (S.linkage == kComplete) {
     k_pair_prep_comp<<<nblk(npairs, 2048), kBlock, 0, s>>>(S, S.pr_cbase);
-    scan_exclusive_i64(S.pr_cbase, S.pr_cbase, npairs, nullptr, &S.cnt->n_chunks, S.part, s);
+    scan_exclusive_i64(S.pr_cbase, S.pr_cbase, npairs, nullptr, &S.cnt->n_chunks, S.sws, s);
   } else {
     k_pair_tiles<<<nblk(npairs, 2048), kBlock, 0, s>>>(S, tmp);
-    scan_exclusive_i64(tmp, S.pr_tile0, npairs, nullptr, &S.cnt->n_tiles, S.part, s);
+    scan_exclusive_i64(tmp, S.pr_tile0, npairs, nullptr, &S.cnt->n_tiles, S.sws, s);
   }
 }
 
@@ -3985,7 +4169,7 @@ void launch_pairs(State &S, int round, int npairs, long long work, hipStream_t s
     if (S.linkage == kComplete) {
       k_filter_comp<<<(int)std::min<long long>(work, 1 << 20), kBlock, 0, s>>>(S, work);
       k_pair_tiles_f<<<nblk(npairs, 2048), kBlock, 0, s>>>(S, S.pr_tile0);
-      scan_exclusive_i64(S.pr_tile0, S.pr_tile0, npairs, nullptr, &S.cnt->n_tiles, S.part, s);
+      scan_exclusive_i64(S.pr_tile0, S.pr_tile0, npairs, nullptr, &S.cnt->n_tiles, S.sws, s);
       tmark(S, 2, false, s);
       if (S.d <= 2) k_tiles_comp<2><<<2048, kBlock, 0, s>>>(S);
       else if (S.d <= 4) k_tiles_comp<4><<<2048, kBlock, 0, s>>>(S);
@@ -4018,7 +4202,7 @@ void launch_round_tail(State &S, int round, int nact, int merges_before, hipStre
   const int gb = nblk(nact, 2048);
   k_chain<<<gb, kBlock, 0, s>>>(S);
   k_rnn_flags<<<gb, kBlock, 0, s>>>(S, round);
-  scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_term, &S.cnt->n_merge, S.part, s);
+  scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_term, &S.cnt->n_merge, S.sws, s);
   k_rnn_scatter<<<gb, kBlock, 0, s>>>(S);
   k_merge<<<nblk(nact / 2 + 1, 2048), kBlock, 0, s>>>(S, merges_before);
   if (S.linkage == kComplete && S.d == 2)
@@ -4026,13 +4210,13 @@ void launch_round_tail(State &S, int round, int nact, int merges_before, hipStre
   if (S.timing) (void)hipEventRecord(S.rev[2], s);
   k_alive_flags<<<gb, kBlock, 0, s>>>(S);
   int *total = S.scan + S.n;  // one spare int past the scan array
-  scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, total, S.part, s);
+  scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, total, S.sws, s);
   k_scatter_flagged<<<gb, kBlock, 0, s>>>(S.act, S.flags, S.scan, &S.cnt->n_act, S.act2);
   k_swap_count<<<1, 1, 0, s>>>(S.cnt, total);
   std::swap(S.act, S.act2);
   if (!centroid_link(S.linkage)) {
     k_sizes_of_act<<<gb, kBlock, 0, s>>>(S);
-    scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, nullptr, S.part, s);
+    scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, nullptr, S.sws, s);
     k_set_nbeg<<<gb, kBlock, 0, s>>>(S);
     k_move_points<<<nblk(S.n, 4096), kBlock, 0, s>>>(S);
     k_copy_beg<<<gb, kBlock, 0, s>>>(S);
@@ -4046,9 +4230,9 @@ void launch_finalize(State &S, void *out_rows, hipStream_t s) {
   if (m <= 0) return;
   const int b = nblk(m, 1 << 22);
   k_row_keys2<<<b, kBlock, 0, s>>>(S, m);
-  radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, m, 64, S.hist, S.part, s);
+  radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, m, 64, S.hist, S.sws, s);
   k_row_keys1<<<b, kBlock, 0, s>>>(S, m);
-  radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, m, 64, S.hist, S.part, s);
+  radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, m, 64, S.hist, S.sws, s);
   k_newid<<<b, kBlock, 0, s>>>(S, m);
   k_write_rows<<<b, kBlock, 0, s>>>(S, m, (OutRow *)out_rows);
 }

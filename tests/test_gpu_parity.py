@@ -223,13 +223,18 @@ def test_cache_d10_average(pc):
     assert same_rows(Z0, Z1, "average") and st["cache_hits"] > 0
 
 
-@pytest.mark.parametrize("link", ["complete", "average"])
-def test_cache_high_dim(pc, link):
-    """d = 64 (Gram search): cached and combined values against none."""
-    x = synth.sphere_blobs(2000, 64, 20, 0.1, 43)
+@pytest.mark.parametrize("link,d", [("complete", 12), ("complete", 64), ("average", 64)])
+def test_cache_high_dim(pc, link, d):
+    """Gram search (d >= 4): cached and combined values against none. Above
+    d = 16 the interval tiles settle every larger complete-linkage value
+    exactly, so no complete pair reaches the cache there; at d = 12 the
+    exact pass, and with it the cache, still serves them."""
+    x = synth.sphere_blobs(2000, d, 20, 0.1, 43)
     Z0 = pc.hac(x, link, cache_slots=0)
     Z1, st = pc.hac(x, link, cache_slots=64, return_stats=True)
-    assert same_rows(Z0, Z1, link) and st["cache_derived"] > 0
+    assert same_rows(Z0, Z1, link)
+    if link == "average" or d <= 16:
+        assert st["cache_derived"] > 0
     Zo, _ = oracle.nnchain(x, link, threads=8)
     assert _trees.same_tree(Z1, Zo, 2000, rtol=RTOL[link])
 
