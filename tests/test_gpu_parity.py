@@ -283,6 +283,21 @@ def test_interval_screening(pc, link, d):
     assert same_rows(Zg, Z0, link)
 
 
+def test_complete_tiles_settle_fallback(pc):
+    """Complete linkage above d = 16 takes exact keys inside the interval
+    tiles, only of the pairs whose upper bound reaches the candidate's lower
+    bound. Groups of near-identical points put every cross pair inside the
+    FP16 bracket, so a wavefront meets more qualifying pairs than it settles
+    and the candidate must go to the exact FP64 tiles instead: the rows must
+    still be the oracle's, bit for bit."""
+    rng = np.random.default_rng(71)
+    g, m, d = 6, 80, 64
+    cen = rng.normal(0.0, 3.0, (g, d))
+    x = (np.repeat(cen, m, axis=0) + rng.uniform(-1e-4, 1e-4, (g * m, d))).astype(np.float32)
+    Zg, st, _ = check_parity(pc, x, "complete", timing=True)
+    assert st["kernels"]["pair_tiles"]["launches"] > 0  # the settling pass and the exact tiles
+
+
 def test_avgsq_hand_computed_instances(pc):
     """avg-2 heights worked out by hand from the double-sum definition (the
     oracle's own pin), now from the GPU path."""
