@@ -846,7 +846,9 @@ __device__ __forceinline__ double key_to_height(int link, double v) {
 // average, the search bound plus the best inline-evaluated candidate. PASS 1
 // (complete/average): re-walk the rings under the final bound and emit the
 // large pairs whose lower bound does not exceed it.
-template <int LINK, int MAXD, int PASS>
+// CACHE: the call keeps a pair cache (compiled out otherwise: its probes
+// cost registers, hence occupancy, in every search)
+template <int LINK, int MAXD, int PASS, bool CACHE>
 __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
   const int nterm = S.cnt->n_term;
   const int ti = blockIdx.x * blockDim.x + threadIdx.x;
@@ -969,7 +971,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                 const double cur = PASS == 0 ? fmin(bound, bestv) : bound;
                 if (lb > cur * kSlack) continue;
                 const long long cost = (long long)n_t * (long long)mt.y;
-                if (PASS == 0 && cost > kInlinePairs && S.cache_mask) {
+                if (CACHE && PASS == 0 && cost > kInlinePairs) {
                   double v;
                   if (cache_find(S, pair_key(S.node[t], S.node[s]), v) == 1) {
                     ++hits;
@@ -1028,7 +1030,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
                 } else if (PASS == 0) {
                   if (ub < bound) bound = ub;
                 } else {
-                  if (S.cache_mask) {
+                  if (CACHE) {
                     double v;
                     if (cache_find(S, pair_key(S.node[t], S.node[s]), v) == 1) continue;  // counted in pass 0
                     if (pend_if_resolved(S, ti, s)) continue;
@@ -1142,7 +1144,7 @@ __device__ __forceinline__ double cell_key_lb(double D, double nt, int cnmin) {
   return D;
 }
 
-template <int LINK, int MAXD>
+template <int LINK, int MAXD, bool CACHE>
 __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
   __shared__ double red_v[kBlock / kWave], red_b[kBlock / kWave];
   __shared__ unsigned long long red_k[kBlock / kWave];
@@ -1250,7 +1252,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
               const double c2 = pass == 0 ? fmin(cur, fmin(bound, bestv)) : cur;
               if (lb > c2 * kSlack) continue;
               const long long cost = (long long)n_t * (long long)mt.y;
-              if (pass == 0 && cost > kInlinePairs && S.cache_mask) {
+              if (CACHE && pass == 0 && cost > kInlinePairs) {
                 double v;
                 if (cache_find(S, pair_key(S.node[t], S.node[sl]), v) == 1) {
                   ++hits;
@@ -1284,7 +1286,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_ringblk(State S) {
               } else if (pass == 0) {
                 if (ub < bound) bound = ub;
               } else {
-                if (S.cache_mask) {
+                if (CACHE) {
                   double v;
                   if (cache_find(S, pair_key(S.node[t], S.node[sl]), v) == 1) continue;  // counted in pass 0
                   if (pend_if_resolved(S, ti, sl)) continue;
@@ -3809,23 +3811,46 @@ inline void tmark(State &S, int k, bool end, hipStream_t s) {
   if (end) S.tlaunched[k] = 1;
 }
 
+// the ring searches with or without the cache probes (centroid linkages
+// never probe)
+template <int LINK, int MAXD, int PASS>
+void launch_grid(State &S, int tb, hipStream_t s, int *t_ovf) {
+  if constexpr (!centroid_link(LINK)) {
+    if (S.cache_mask) {
+      k_nn_grid<LINK, MAXD, PASS, true><<<tb, kBlock, 0, s>>>(S, t_ovf);
+      return;
+    }
+  }
+  k_nn_grid<LINK, MAXD, PASS, false><<<tb, kBlock, 0, s>>>(S, t_ovf);
+}
+template <int LINK, int MAXD>
+void launch_ringblk(State &S, int ob, hipStream_t s) {
+  if constexpr (!centroid_link(LINK)) {
+    if (S.cache_mask) {
+      k_nn_ringblk<LINK, MAXD, true><<<ob, kBlock, 0, s>>>(S);
+      return;
+    }
+  }
+  k_nn_ringblk<LINK, MAXD, false><<<ob, kBlock, 0, s>>>(S);
+}
+
 template <int LINK>
 void launch_search(State &S, int nact, hipStream_t s, int *t_ovf) {
   const int tb = nblk(nact, 1 << 20);
   const size_t sm = (size_t)S.d * (sizeof(double) + 2 * sizeof(float));
   if (S.d <= kGridMaxDim && S.prune) {
     tmark(S, 0, false, s);
-    if (S.d <= 2) k_nn_grid<LINK, 2, 0><<<tb, kBlock, 0, s>>>(S, t_ovf);
-    else if (S.d <= 4) k_nn_grid<LINK, 4, 0><<<tb, kBlock, 0, s>>>(S, t_ovf);
-    else if (S.d <= 8) k_nn_grid<LINK, 8, 0><<<tb, kBlock, 0, s>>>(S, t_ovf);
-    else k_nn_grid<LINK, 16, 0><<<tb, kBlock, 0, s>>>(S, t_ovf);
+    if (S.d <= 2) launch_grid<LINK, 2, 0>(S, tb, s, t_ovf);
+    else if (S.d <= 4) launch_grid<LINK, 4, 0>(S, tb, s, t_ovf);
+    else if (S.d <= 8) launch_grid<LINK, 8, 0>(S, tb, s, t_ovf);
+    else launch_grid<LINK, 16, 0>(S, tb, s, t_ovf);
     tmark(S, 0, true, s);
     tmark(S, 1, false, s);
     const int ob = nblk((long long)nact * kBlock, 2048);
-    if (S.d <= 2) k_nn_ringblk<LINK, 2><<<ob, kBlock, 0, s>>>(S);
-    else if (S.d <= 4) k_nn_ringblk<LINK, 4><<<ob, kBlock, 0, s>>>(S);
-    else if (S.d <= 8) k_nn_ringblk<LINK, 8><<<ob, kBlock, 0, s>>>(S);
-    else k_nn_ringblk<LINK, 16><<<ob, kBlock, 0, s>>>(S);
+    if (S.d <= 2) launch_ringblk<LINK, 2>(S, ob, s);
+    else if (S.d <= 4) launch_ringblk<LINK, 4>(S, ob, s);
+    else if (S.d <= 8) launch_ringblk<LINK, 8>(S, ob, s);
+    else launch_ringblk<LINK, 16>(S, ob, s);
     tmark(S, 1, true, s);
   } else {
     tmark(S, 1, false, s);
@@ -3866,10 +3891,10 @@ void launch_emit(State &S, int nact, hipStream_t s, int *t_ovf) {
   if (S.d <= kGridMaxDim && S.prune) {
     const int tb = nblk(nact, 1 << 20);
     tmark(S, 3, false, s);
-    if (S.d <= 2) k_nn_grid<LINK, 2, 1><<<tb, kBlock, 0, s>>>(S, t_ovf);
-    else if (S.d <= 4) k_nn_grid<LINK, 4, 1><<<tb, kBlock, 0, s>>>(S, t_ovf);
-    else if (S.d <= 8) k_nn_grid<LINK, 8, 1><<<tb, kBlock, 0, s>>>(S, t_ovf);
-    else k_nn_grid<LINK, 16, 1><<<tb, kBlock, 0, s>>>(S, t_ovf);
+    if (S.d <= 2) launch_grid<LINK, 2, 1>(S, tb, s, t_ovf);
+    else if (S.d <= 4) launch_grid<LINK, 4, 1>(S, tb, s, t_ovf);
+    else if (S.d <= 8) launch_grid<LINK, 8, 1>(S, tb, s, t_ovf);
+    else launch_grid<LINK, 16, 1>(S, tb, s, t_ovf);
     tmark(S, 3, true, s);
   }
 }
