@@ -82,6 +82,10 @@ typedef struct {
     int64_t size;
 } pc_merge;
 
+/* pc_options.timing bits */
+#define PC_TIME_KERNELS 1
+#define PC_TIME_PHASES 2
+
 /* Options; pass NULL for defaults. struct_size must be sizeof(pc_options). */
 typedef struct {
     uint32_t struct_size;
@@ -89,8 +93,11 @@ typedef struct {
     int32_t prune;     /* 1 (default): range-query pruning (Sec. 4);
                           0: every terminal scans every active cluster
                           (same result, for ablations and tests) */
-    int32_t timing;    /* 1: time the search and tile kernels with HIP events
-                          on the call's stream (fills the kernel_* stats) */
+    int32_t timing;    /* bit 0 (PC_TIME_KERNELS): time the search and tile
+                          kernels with HIP events on the call's stream (fills
+                          the kernel_* stats); bit 1 (PC_TIME_PHASES): also
+                          the rounds by phase (ms_nn, ms_merge, ms_update; 4
+                          more events and 3 host reads per round). 0: none */
     int32_t cache_slots; /* cluster-pair distance cache (Alg. 4, Sec. 5):
                           capacity ~ cache_slots * n entries; -1 = default
                           (64 for average, 0 = off for complete, the paper's
@@ -112,7 +119,7 @@ typedef struct {
     double ms_init;           /* layout + first grid */
     double ms_rounds;         /* all rounds */
     double ms_finalize;       /* sort rows + relabel */
-    /* with pc_options.timing: summed device time and launch count of the
+    /* with PC_TIME_KERNELS: summed device time and launch count of the
      * search/evaluation kernels (HIP events around each launch) */
     double kernel_ms[4];      /* [0] search: ring search (bound pass), box-tree
                                  search or Gram pass 0; [1] block ring search,
@@ -131,7 +138,7 @@ typedef struct {
     int64_t fp64_fallbacks;   /* of those, the ones beyond one per screened
                                  chain tail: FP64 work owed to the tiles'
                                  error bounds */
-    /* with pc_options.timing: device time of the rounds by phase */
+    /* with PC_TIME_PHASES: device time of the rounds by phase */
     double ms_nn;             /* terminals, spatial index, nearest-neighbour
                                  search and candidate evaluation */
     double ms_merge;          /* chain update, reciprocal pairs, merges */

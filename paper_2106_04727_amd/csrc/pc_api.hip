@@ -208,7 +208,7 @@ struct pc_context {
   hipError_t scratch_error = hipSuccess;
   Counters *hcnt = nullptr;  // pinned host mirror of the device counters
   hipEvent_t ev[4] = {};
-  hipEvent_t tev[8] = {};
+  KTimer ktimer;              // kernel event pool and log
   hipEvent_t rev[4] = {};    // per round: start, search done, merge done, end
   std::atomic<int> busy{0};
 };
@@ -268,8 +268,7 @@ pc_status pc_context_create(int device, size_t hbm_budget_bytes, pc_context **ou
   hipError_t e = set_direction_table();
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hcnt, sizeof(Counters), hipHostMallocDefault);
   for (int i = 0; e == hipSuccess && i < 4; ++i) e = hipEventCreate(&c->ev[i]);
-  for (int i = 0; e == hipSuccess && i < 8; ++i) e = hipEventCreate(&c->tev[i]);
-  for (int i = 0; e == hipSuccess && i < 4; ++i) e = hipEventCreate(&c->rev[i]);
+  for (int i = 0; e == hipSuccess && i < 4; ++i) e = hipEventCreateWithFlags(&c->rev[i], hipEventDisableSystemFence);
   if (e == hipSuccess) {
     // the allocation-free entry point's array on this device; a failure here
     // is reported by that entry point (c->scratch stays null), not by pc_hac
@@ -325,8 +324,7 @@ void pc_context_destroy(pc_context *c) {
   if (c->hcnt) hipHostFree(c->hcnt);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) hipEventDestroy(c->ev[i]);
-  for (int i = 0; i < 8; ++i)
-    if (c->tev[i]) hipEventDestroy(c->tev[i]);
+  for (hipEvent_t ev : c->ktimer.pool) hipEventDestroy(ev);
   for (int i = 0; i < 4; ++i)
     if (c->rev[i]) hipEventDestroy(c->rev[i]);
   delete c;
@@ -575,7 +573,8 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
   S.d = d;
   S.linkage = linkage;
   S.prune = prune;
-  S.timing = (opt && opt->timing) ? 1 : 0;
+  S.timing = (opt && (opt->timing & PC_TIME_KERNELS)) ? 1 : 0;
+  S.phases = (opt && (opt->timing & PC_TIME_PHASES)) ? 1 : 0;
   // Ward and avg-2 at 3 <= d <= 5 search a box tree over Morton-ordered
   // centroids while many clusters are active and the Gram search once at most
   // tree_gram_switch are (at d = 3, where there is no Gram search, the tree
@@ -594,21 +593,16 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
   // the first round's search (tree_ok also fixes the Morton order of the init)
   S.tree = tree_ok ? 1 : 0;
   S.gram = (!tree_ok && gram_ok) ? 1 : 0;
-  S.tev = ctx->tev;
+  S.kt = &ctx->ktimer;
+  S.kt->begin_call();
   S.rev = ctx->rev;
   S.xin = nullptr;  // set once the device copy of the points is known
   double kms[4] = {0, 0, 0, 0};
   long long klaunch[4] = {0, 0, 0, 0};
-  // after a synchronisation: add the timed kernels of the last round
+  // after a synchronisation: the timed launches so far stand (a redo from
+  // here on drops only its own); the times are read at the end of the call
   auto take_times = [&]() {
-    if (!S.timing) return;
-    for (int k = 0; k < 4; ++k)
-      if (S.tlaunched[k]) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, S.tev[2 * k], S.tev[2 * k + 1]) == hipSuccess) kms[k] += ms;
-        ++klaunch[k];
-        S.tlaunched[k] = 0;
-      }
+    if (S.timing) S.kt->commit();
   };
   float *xdev = (float *)points;
   if (!points_on_device) {
@@ -698,7 +692,7 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
   Counters &h = *ctx->hcnt;
   while (nact > 1) {
     if (rounds > n) return fail(PC_ERR_DEVICE, "round loop did not converge");
-    if (S.timing) HIPCHK(hipEventRecord(ctx->rev[0], s));
+    if (S.phases) HIPCHK(hipEventRecord(ctx->rev[0], s));
     if (tree_ok) {
       const bool use_tree = !gram_ok || tree_gram_switch <= 0 || nact > tree_gram_switch;
       S.tree = use_tree ? 1 : 0;
@@ -777,7 +771,7 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
         if (h.cand_overflow || pover) {
           // redo this batch: larger buffers while they stay within the limit,
           // otherwise fewer terminals per batch
-          S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;
+          if (S.timing) S.kt->drop();
           launch_cache_unclaim(S, s);
           bool shrink = false;
           // (beyond the record limit or the context's budget: fewer terminals)
@@ -814,7 +808,7 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
           if (st != PC_OK) return st;
           if (too_big) {
             // fewer terminals per batch; the claims of this batch are dropped
-            S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;
+            if (S.timing) S.kt->drop();
             launch_cache_unclaim(S, s);
             if (t1 - t0 <= 1) return fail(PC_ERR_OUT_OF_MEMORY, "one terminal's pair evaluation exceeds the limits");
             tb = std::max<long long>(1, (t1 - t0) / 4);
@@ -844,7 +838,7 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
         }
       }
       if (h.n_pairs > S.pair_cap || h.n_pend > S.pair_cap) {
-        S.tlaunched[0] = S.tlaunched[1] = S.tlaunched[2] = S.tlaunched[3] = 0;  // the round is redone
+        if (S.timing) S.kt->drop();  // the round is redone
         launch_cache_unclaim(S, s);
         const long long want = std::max<long long>(h.n_pairs, h.n_pend);
         pc_status st = grow_pairs(ctx, S, std::max<long long>(want, std::min<long long>(want + want / 2 + 1024, kMaxRecord)));
@@ -867,13 +861,13 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
       if (too_big) return fail(PC_ERR_OUT_OF_MEMORY, "a round's pair evaluation exceeds the record limits");
     }
     if (S.gram) gram_terms += h.n_term;
-    if (S.timing) HIPCHK(hipEventRecord(ctx->rev[1], s));
-    launch_round_tail(S, (int)rounds, nact, merges, s);  // records rev[2] after the merges when timing
+    if (S.phases) HIPCHK(hipEventRecord(ctx->rev[1], s));
+    launch_round_tail(S, (int)rounds, nact, merges, s);  // records rev[2] after the merges (phases)
     HIPCHK(hipGetLastError());
-    if (S.timing) HIPCHK(hipEventRecord(ctx->rev[3], s));
+    if (S.phases) HIPCHK(hipEventRecord(ctx->rev[3], s));
     HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (S.timing) {
+    if (S.phases) {
       float a = 0.f, b = 0.f, c = 0.f;
       if (hipEventElapsedTime(&a, ctx->rev[0], ctx->rev[1]) == hipSuccess) ms_nn += a;
       if (hipEventElapsedTime(&b, ctx->rev[1], ctx->rev[2]) == hipSuccess) ms_merge += b;
@@ -919,6 +913,16 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
     HIPCHK(hipMemcpyAsync(out, dout, (size_t)(n - 1) * sizeof(pc_merge), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&h, S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (S.timing) {
+    // every timed launch has completed: read the log once
+    KTimer &t = *S.kt;
+    t.commit();
+    for (size_t j = 0; j + 2 < t.kept; j += 3) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, t.pool[t.done[j + 1]], t.pool[t.done[j + 2]]) == hipSuccess) kms[t.done[j]] += ms;
+      ++klaunch[t.done[j]];
+    }
+  }
   if (stats) {
     float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
     hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);

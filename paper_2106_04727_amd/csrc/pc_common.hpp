@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 namespace pc {
 
@@ -156,6 +157,39 @@ struct ScanWs {
   int *err;     // device: Counters::scan_err
 };
 
+// Kernel timing (host side): every timed launch records a start and an end
+// event from a pool the context keeps across calls; the elapsed times are
+// read once, after the call's last synchronisation, so no round waits on
+// them. Marks recorded since the last commit belong to an attempt that may
+// be redone and are dropped with it.
+struct KTimer {
+  std::vector<hipEvent_t> pool;
+  int next = 0;                      // next unused event of this call
+  int open[4] = {-1, -1, -1, -1};    // start event of each slot's running launch
+  std::vector<int> done;             // (slot, start, end) triples
+  size_t kept = 0;                   // entries of `done` committed
+  hipError_t take(int &idx) {
+    if (next == (int)pool.size()) {
+      // timing only, read after a stream synchronisation: no system-scope
+      // fence (its cache writeback would slow the work that follows)
+      hipEvent_t e;
+      hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
+      if (r != hipSuccess) return r;
+      pool.push_back(e);
+    }
+    idx = next++;
+    return hipSuccess;
+  }
+  void begin_call() {
+    next = 0;
+    done.clear();
+    kept = 0;
+    for (int &o : open) o = -1;
+  }
+  void commit() { kept = done.size(); }
+  void drop() { done.resize(kept); }
+};
+
 // All device arrays of one clustering call. Slots are storage indices of
 // clusters (capacity n); a merged cluster keeps the slot of its child with
 // the lower cluster ID. Lists hold slots.
@@ -283,9 +317,10 @@ struct State {
   int cell_cap;
   // optional kernel timing: event pairs around ring search, full scan, tiles
   int timing;
-  hipEvent_t *tev;      // 8 events (start/end per kernel), owned by the context
+  int phases;           // (host) also time the rounds by phase
+  struct KTimer *kt;    // kernel event log (host), owned by the context
   hipEvent_t *rev;      // 4 events per round (start, search done, merge done, end)
-  int tlaunched[4];     // kernels launched since the last read (host side)
+
 };
 
 // ------------------------------------------------------ launch wrappers ----

@@ -3807,8 +3807,18 @@ inline int nblk(long long n, int cap = 4096) {
 
 inline void tmark(State &S, int k, bool end, hipStream_t s) {
   if (!S.timing) return;
-  (void)hipEventRecord(S.tev[2 * k + (end ? 1 : 0)], s);
-  if (end) S.tlaunched[k] = 1;
+  KTimer &t = *S.kt;
+  int idx;
+  if (t.take(idx) != hipSuccess) return;  // (no event: this launch goes untimed)
+  (void)hipEventRecord(t.pool[idx], s);
+  if (!end) {
+    t.open[k] = idx;
+  } else if (t.open[k] >= 0) {
+    t.done.push_back(k);
+    t.done.push_back(t.open[k]);
+    t.done.push_back(idx);
+    t.open[k] = -1;
+  }
 }
 
 // the ring searches with or without the cache probes (centroid linkages
@@ -4232,7 +4242,7 @@ void launch_round_tail(State &S, int round, int nact, int merges_before, hipStre
   k_merge<<<nblk(nact / 2 + 1, 2048), kBlock, 0, s>>>(S, merges_before);
   if (S.linkage == kComplete && S.d == 2)
     k_merge_sup<<<nblk((long long)(nact / 2 + 1) * kSupDirs, 8192), kBlock, 0, s>>>(S);
-  if (S.timing) (void)hipEventRecord(S.rev[2], s);
+  if (S.phases) (void)hipEventRecord(S.rev[2], s);
   k_alive_flags<<<gb, kBlock, 0, s>>>(S);
   int *total = S.scan + S.n;  // one spare int past the scan array
   scan_exclusive_i32(S.flags, S.scan, nact, &S.cnt->n_act, total, S.sws, s);

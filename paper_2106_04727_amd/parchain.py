@@ -183,8 +183,18 @@ def _prec(precision) -> int:
     return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
 
 
+TIME_KERNELS, TIME_PHASES = 1, 2  # pc_options.timing bits
+
+
+def _timing(timing) -> int:
+    """True: kernels and round phases; "kernels": the kernel events only."""
+    if timing == "kernels":
+        return TIME_KERNELS
+    return TIME_KERNELS | TIME_PHASES if timing else 0
+
+
 def _options(prune=True, timing=False, cache_slots=-1, precision="fp16") -> pc_options:
-    return pc_options(ctypes.sizeof(pc_options), _prec(precision), 1 if prune else 0, 1 if timing else 0,
+    return pc_options(ctypes.sizeof(pc_options), _prec(precision), 1 if prune else 0, _timing(timing),
                       int(cache_slots), 0)
 
 
