@@ -72,6 +72,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_lb(const T *in, T *out, int nma
   for (int j = bid * kBlock + threadIdx.x; j < cap; j += gridDim.x * kBlock) st_next[j] = 0ull;
   if (bid == 0 && threadIdx.x == 0) *ticket_next = 0;
   const int len = scan_len<T>(nmax, dlen);
+  // blocks past the device length have nothing to scan (the grid is sized
+  // for the host's bound); the last live block writes the total
+  const int live = len > 0 ? (len + kScanTile - 1) / kScanTile : 1;
+  if (bid >= live) return;  // uniform per block
   const long long base = (long long)bid * kScanTile + threadIdx.x * kScanItems;
   T v[kScanItems];
   T s = 0;
@@ -124,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_lb(const T *in, T *out, int nma
     }
     if (lane == 0) {
       sprefix = prefix;
-      if (bid == (int)gridDim.x - 1) {
+      if (bid == live - 1) {
         if (total64) *total64 = (long long)(prefix + tot);
         if (total32) *total32 = (int)(prefix + tot);
       }

@@ -3762,10 +3762,11 @@ __global__ void k_copy_beg(State S) {
 __global__ void k_swap_count(Counters *c, int *total_slot) { c->n_act = *total_slot; }
 
 // --------------------------------------------------------------- finalize --
-__global__ void k_row_keys2(State S, int m) {
+// (size, lowest point index): both below 2^lob, packed into 2 lob bits
+__global__ void k_row_keys2(State S, int m, int lob) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= m) return;
-  S.sk0[r] = ((unsigned long long)(unsigned)S.row_size[r] << 32) | (unsigned)S.row_lo[r];
+  S.sk0[r] = ((unsigned long long)(unsigned)S.row_size[r] << lob) | (unsigned)S.row_lo[r];
   S.sv0[r] = (unsigned)r;
 }
 __global__ void k_row_keys1(State S, int m) {
@@ -4264,8 +4265,11 @@ void launch_finalize(State &S, void *out_rows, hipStream_t s) {
   const int m = S.n - 1;
   if (m <= 0) return;
   const int b = nblk(m, 1 << 22);
-  k_row_keys2<<<b, kBlock, 0, s>>>(S, m);
-  radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, m, 64, S.hist, S.sws, s);
+  // sizes and point indices are at most n: the key needs 2 lob bits only
+  int lob = 1;
+  while ((1LL << lob) <= (long long)S.n) ++lob;
+  k_row_keys2<<<b, kBlock, 0, s>>>(S, m, lob);
+  radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, m, 2 * lob, S.hist, S.sws, s);
   k_row_keys1<<<b, kBlock, 0, s>>>(S, m);
   radix_sort_pairs(S.sk0, S.sk1, S.sv0, S.sv1, m, 64, S.hist, S.sws, s);
   k_newid<<<b, kBlock, 0, s>>>(S, m);
