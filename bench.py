@@ -96,13 +96,14 @@ def roofline(kname, link, d, ms, nl, sts):
         r = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VEC_TFLOPS, "unit": "TFLOP/s",
              "note": "exact FP64 point-pair tiles; work = point pairs x FP64 flops per pair"}
     elif link in ("ward", "avgsq") and 3 <= d <= 5 and kname == "ring_search":
-        # the box-tree walk (the rounds with many active clusters; later rounds'
-        # Gram pass 0 shares the timing slot but takes a small part of it):
-        # a gather kernel, one visit = a candidate record or a node box
-        work = visits * visit_bytes(link, d) / nl
-        achieved = work / (avg_ms / 1000.0) / 1e9
-        r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-             "note": "box-tree search: visits x record bytes (the slot also holds Gram pass 0 rounds)"}
+        # the slot holds the box-tree walk (gathers) of the rounds with many
+        # active clusters and Gram pass 0 (MFMA pairs) of the later ones, and
+        # its visit count adds both: no single unit prices it
+        r = {"bound": None, "achieved": None, "peak": None, "unit": None,
+             "note": "box-tree walk and Gram pass 0 share this timing slot; not priced"}
+        r.update({"frac": None, "traffic": None, "kernel": kname, "linkage": link, "avg_launch_ms": avg_ms,
+                  "launches": nl, "work_per_launch": None})
+        return r
     elif gram and kname in ("ring_search", "ring_emit", "block_search"):
         # Gram passes (centroid pairs, K = d + 2 padded) and interval tiles
         # (point pairs, K = d padded): FP16 MFMA, 2 x K flops per pair
