@@ -3154,20 +3154,29 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
     ba = __builtin_amdgcn_readfirstlane(ds.x + r0);
     bb = __builtin_amdgcn_readfirstlane(ds.z + c0);
   };
+  // consecutive tiles of a candidate share their rows (tiles run row by
+  // row): those are kept in LDS and only the columns are loaded again
+  int last_ba = -1, last_nr = -1;
+  bool cur_reuse = false;
   auto fetch = [&](long long tile) {
     locate(tile);
+    const bool reuse = ba == last_ba && nr == last_nr;
+    last_ba = ba;
+    last_nr = nr;
 #pragma unroll
     for (int u = 0; u < NCH; ++u) {
       const int j = threadIdx.x + u * kBlock;
       uint4 v = make_uint4(0, 0, 0, 0);
       if (j < 2 * kGT * CH) {
         const int sd = j / (kGT * CH), r = (j / CH) % kGT, c8 = j % CH;
-        if (r < (sd ? nc : nr)) v = *(const uint4 *)(pts + (size_t)((sd ? bb : ba) + r) * KP + c8 * EPC);
+        if (r < (sd ? nc : nr) && (sd || !reuse))
+          v = *(const uint4 *)(pts + (size_t)((sd ? bb : ba) + r) * KP + c8 * EPC);
       }
       reg[u] = v;
     }
     rq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (w < 2 && lane < (w ? nc : nr)) rq = S.pq[(w ? bb : ba) + lane];
+    if (w < 2 && lane < (w ? nc : nr) && (w || !reuse)) rq = S.pq[(w ? bb : ba) + lane];
+    cur_reuse = reuse;
     cur_i = oi;
     cur_nr = nr;
     cur_nc = nc;
@@ -3236,13 +3245,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
   long long tile = next_tile(ta);
   while (tile < te) {
     const int i = cur_i, nr = cur_nr, ncl = cur_nc, kc = cur_k, ta0 = cur_ba, tb0 = cur_bb;
+    const bool keep_rows = cur_reuse;  // the rows in LDS are this tile's
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NCH; ++u) {
       const int j = threadIdx.x + u * kBlock;
       if (j < 2 * kGT * CH) {
         const int sd = j / (kGT * CH), r = (j / CH) % kGT, c8 = j % CH;
-        *(uint4 *)&sab[sd][r][c8 * EPC] = reg[u];
+        if (sd || !keep_rows) *(uint4 *)&sab[sd][r][c8 * EPC] = reg[u];
       }
     }
     if (prune && threadIdx.x == 0) {
@@ -3250,7 +3260,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
       snap_lb = __hip_atomic_load(&S.cd_lb[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       snap_own = own;
     }
-    if (w < 2) {
+    if (w < 2 && (w || !keep_rows)) {
       an[w][lane] = rq.x;
       float se = rq.z, me = rq.z, mx = rq.y;
       for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -3266,11 +3276,16 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
     }
     __syncthreads();
     const long long nxt = next_tile(tile + 1);  // its points in flight during the tile's arithmetic
+    // a wavefront whose 32 x 32 quarter holds no point pair (small clusters)
+    // skips its matrix and epilogue work; it still meets every barrier
+    const bool wlive = wr < nr && wc < ncl;
     float16v acc = {};
+    if (wlive) {
 #pragma unroll
-    for (int kk = 0; kk < KP; kk += KS)
-      acc = El<EL>::mma(&sab[0][wr + (lane & 31)][kk + (lane >> 5) * (KS / 2)],
-                       &sab[1][wc + (lane & 31)][kk + (lane >> 5) * (KS / 2)], acc);
+      for (int kk = 0; kk < KP; kk += KS)
+        acc = El<EL>::mma(&sab[0][wr + (lane & 31)][kk + (lane >> 5) * (KS / 2)],
+                         &sab[1][wc + (lane & 31)][kk + (lane >> 5) * (KS / 2)], acc);
+    }
     const int col = wc + (lane & 31);
     const bool cval = col < ncl;
     const float cn = an[1][col];
@@ -3279,7 +3294,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
     const float rE = __builtin_amdgcn_sqrtf(Ef) * kGMargin;
     float sum = 0.0f, smin = INFINITY, mx = -INFINITY;
     int cnt = 16;
-    if (nr == kGT && ncl == kGT) {
+    if (!wlive) {
+      cnt = 0;
+    } else if (nr == kGT && ncl == kGT) {
       // full tile: no masks
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
