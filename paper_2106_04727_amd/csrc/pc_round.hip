@@ -2109,8 +2109,12 @@ __global__ __launch_bounds__(kBlock) void k_tiles_hd(State S) {
         const int pb = LINK == kAverage ? begB + c0 + i : S.fidx[region + begB + c0 + i];
         b = S.px[(size_t)pb * d + k];
       }
-      As[k][i] = a;
-      Bs[k][i] = b;
+      // column position swizzled by k (XOR of a multiple of 4): the lanes of a
+      // wavefront store to eight banks instead of one, and every aligned
+      // group of four stays contiguous for the float4 reads below
+      const int sw = i ^ ((k & 7) << 2);
+      As[k][sw] = a;
+      Bs[k][sw] = b;
     }
     __syncthreads();
     double q[4][4];
@@ -2119,8 +2123,9 @@ __global__ __launch_bounds__(kBlock) void k_tiles_hd(State S) {
 #pragma unroll
       for (int b = 0; b < 4; ++b) q[a][b] = 0.0;
     for (int k = 0; k < d; ++k) {
-      const float4 av = *(const float4 *)&As[k][ty * 4];
-      const float4 bv = *(const float4 *)&Bs[k][tx * 4];
+      const int sk = (k & 7) << 2;
+      const float4 av = *(const float4 *)&As[k][(ty * 4) ^ sk];
+      const float4 bv = *(const float4 *)&Bs[k][(tx * 4) ^ sk];
       const double ar[4] = {(double)av.x, (double)av.y, (double)av.z, (double)av.w};
       const double br[4] = {(double)bv.x, (double)bv.y, (double)bv.z, (double)bv.w};
 #pragma unroll
