@@ -261,9 +261,12 @@ typedef struct {
     int64_t requeued;         /* requests sent back to the queue with a larger reservation */
 } pc_server_stats;
 
-/* Create a server on HIP device `device` (current device if < 0); opt may be
- * NULL. Each slot holds a context and a non-blocking stream of its own. */
-pc_status pc_server_create(int device, const pc_server_options *opt, pc_server **out);
+/* Create a server on the device of `ctx` (the caller's current device if ctx
+ * is NULL); opt may be NULL. The server does not use ctx itself, which stays
+ * the caller's: each slot holds a context and a non-blocking stream of its
+ * own on that device. In the no-device test mode (fake_us_per_kpoint > 0)
+ * ctx is ignored. */
+pc_status pc_server_create(pc_context *ctx, const pc_server_options *opt, pc_server **out);
 
 /* Queue a request. `points` (host, float32, n x d row-major) and `out` (host,
  * n-1 rows) stay owned by the caller and must stay valid until the request
@@ -274,8 +277,16 @@ pc_status pc_server_create(int device, const pc_server_options *opt, pc_server *
 pc_status pc_server_submit(pc_server *srv, const float *points, int64_t n, int32_t d, int32_t linkage,
                            const pc_options *opt, pc_merge *out, uint64_t *ticket);
 
-/* State of a request (info may be NULL). Unknown tickets: PC_ERR_INVALID_ARG. */
-pc_status pc_server_poll(pc_server *srv, uint64_t ticket, pc_request_info *info);
+/* Whether a request has finished: *done = 1 once it is done or cancelled,
+ * then *result is its status (PC_OK, PC_ERR_CANCELLED or the error of pc_hac)
+ * and *stats (struct_size set by the caller) its counters; while it waits or
+ * runs, *done = 0 and *result = PC_ERR_BUSY. Any pointer may be NULL.
+ * Unknown tickets: PC_ERR_INVALID_ARG. */
+pc_status pc_server_poll(pc_server *srv, uint64_t ticket, int *done, pc_status *result, pc_stats *stats);
+
+/* The full record of a request: state, slot, reserved bytes, times, counters
+ * and error text (info may be NULL). Unknown tickets: PC_ERR_INVALID_ARG. */
+pc_status pc_server_query(pc_server *srv, uint64_t ticket, pc_request_info *info);
 
 /* Wait until the request is done or cancelled; timeout_ms < 0 waits without
  * limit. PC_ERR_BUSY when the time runs out (info then shows the state). */

@@ -300,6 +300,7 @@ size_t context_bytes(const pc_context *c) { return held_bytes(c); }
 // the serving layer caps a slot's context at the request's reservation
 void context_set_budget(pc_context *c, size_t bytes) { c->budget = bytes; }
 bool context_over_budget(const pc_context *c) { return c->over_budget; }
+int context_device(const pc_context *c) { return c->device; }
 
 void context_trim(pc_context *c) {
   hipSetDevice(c->device);

@@ -38,6 +38,7 @@ size_t context_bytes(const pc_context *c);
 void context_trim(pc_context *c);
 void context_set_budget(pc_context *c, size_t bytes);
 bool context_over_budget(const pc_context *c);
+int context_device(const pc_context *c);
 void set_error(const char *msg);  // the text pc_last_error() returns on this thread
 }  // namespace pc
 
@@ -214,7 +215,7 @@ struct pc_server {
 
 extern "C" {
 
-pc_status pc_server_create(int device, const pc_server_options *opt, pc_server **out) {
+pc_status pc_server_create(pc_context *ctx, const pc_server_options *opt, pc_server **out) {
   if (!out) return sfail(PC_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (opt && opt->struct_size < sizeof(pc_server_options))
@@ -235,7 +236,7 @@ pc_status pc_server_create(int device, const pc_server_options *opt, pc_server *
   if (s->fake_us > 0.0) {
     if (!s->budget) s->budget = 1ull << 30;
   } else {
-    int dev = device;
+    int dev = ctx ? pc::context_device(ctx) : -1;
     if (dev < 0 && hipGetDevice(&dev) != hipSuccess) {
       delete s;
       return sfail(PC_ERR_DEVICE, "hipGetDevice failed");
@@ -329,7 +330,26 @@ static void fill_info(const Job *j, pc_request_info *info) {
   info->error[m] = 0;
 }
 
-pc_status pc_server_poll(pc_server *s, uint64_t ticket, pc_request_info *info) {
+pc_status pc_server_poll(pc_server *s, uint64_t ticket, int *done, pc_status *result, pc_stats *stats) {
+  if (!s) return sfail(PC_ERR_INVALID_ARG, "server is NULL");
+  if (stats && stats->struct_size < sizeof(pc_stats))
+    return sfail(PC_ERR_INVALID_ARG, "pc_stats.struct_size too small");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return sfail(PC_ERR_INVALID_ARG, "unknown ticket");
+  const Job *j = it->second;
+  const bool fin = j->state == kDone || j->state == kCancelled;
+  if (done) *done = fin ? 1 : 0;
+  if (result) *result = !fin ? PC_ERR_BUSY : (j->state == kCancelled ? PC_ERR_CANCELLED : j->result);
+  if (stats && fin) {
+    const uint32_t size = stats->struct_size;
+    *stats = j->stats;
+    stats->struct_size = size;
+  }
+  return PC_OK;
+}
+
+pc_status pc_server_query(pc_server *s, uint64_t ticket, pc_request_info *info) {
   if (!s) return sfail(PC_ERR_INVALID_ARG, "server is NULL");
   if (info && info->struct_size < sizeof(pc_request_info))
     return sfail(PC_ERR_INVALID_ARG, "pc_request_info.struct_size too small");

@@ -114,8 +114,8 @@ class pc_server_stats(ctypes.Structure):
 
 EXPORTS = ["pc_context_create", "pc_context_destroy", "pc_hac_workspace_bytes", "pc_hac", "pc_hac_noalloc",
            "pc_last_error", "pc_version", "pc_server_create", "pc_server_submit", "pc_server_poll",
-           "pc_server_wait", "pc_server_cancel", "pc_server_release", "pc_server_get_stats",
-           "pc_server_destroy"]
+           "pc_server_query", "pc_server_wait", "pc_server_cancel", "pc_server_release",
+           "pc_server_get_stats", "pc_server_destroy"]
 
 
 def load_library(path: str | None = None):
@@ -144,13 +144,16 @@ def load_library(path: str | None = None):
         lib.pc_last_error.restype = ctypes.c_char_p
         lib.pc_version.argtypes = []
         lib.pc_version.restype = ctypes.c_char_p
-        lib.pc_server_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
+        lib.pc_server_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
         lib.pc_server_create.restype = ctypes.c_int
         lib.pc_server_submit.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp, vp,
                                          ctypes.POINTER(ctypes.c_uint64)]
         lib.pc_server_submit.restype = ctypes.c_int
-        lib.pc_server_poll.argtypes = [vp, ctypes.c_uint64, vp]
+        lib.pc_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int), vp]
         lib.pc_server_poll.restype = ctypes.c_int
+        lib.pc_server_query.argtypes = [vp, ctypes.c_uint64, vp]
+        lib.pc_server_query.restype = ctypes.c_int
         lib.pc_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, vp]
         lib.pc_server_wait.restype = ctypes.c_int
         lib.pc_server_cancel.argtypes = [vp, ctypes.c_uint64]
@@ -332,7 +335,10 @@ class Server:
         opt = pc_server_options(ctypes.sizeof(pc_server_options), int(slots), int(hbm_budget_bytes),
                                 float(fake_us_per_kpoint), float(fake_growth))
         h = ctypes.c_void_p()
-        _check(self.lib, self.lib.pc_server_create(int(device), ctypes.byref(opt), ctypes.byref(h)))
+        # the server runs on this context's device (none in the no-device test mode)
+        self.ctx = Context(device) if fake_us_per_kpoint <= 0.0 else None
+        _check(self.lib, self.lib.pc_server_create(self.ctx.handle if self.ctx else None, ctypes.byref(opt),
+                                                   ctypes.byref(h)))
         self.handle = h
         self._keep = {}
 
@@ -353,9 +359,16 @@ class Server:
         return info
 
     def poll(self, ticket: int) -> dict:
+        """The request's full record (pc_server_query)."""
         info = self._info()
-        _check(self.lib, self.lib.pc_server_poll(self.handle, ticket, ctypes.byref(info)))
+        _check(self.lib, self.lib.pc_server_query(self.handle, ticket, ctypes.byref(info)))
         return info.as_dict()
+
+    def done(self, ticket: int):
+        """(finished, status) of a request (pc_server_poll)."""
+        d, r = ctypes.c_int(), ctypes.c_int()
+        _check(self.lib, self.lib.pc_server_poll(self.handle, ticket, ctypes.byref(d), ctypes.byref(r), None))
+        return bool(d.value), r.value
 
     def wait(self, ticket: int, timeout_ms: float = -1.0) -> dict:
         info = self._info()
@@ -391,6 +404,9 @@ class Server:
             self.lib.pc_server_destroy(self.handle)
             self.handle = None
             self._keep.clear()
+        if getattr(self, "ctx", None):
+            self.ctx.close()
+            self.ctx = None
 
     def __enter__(self):
         return self

@@ -146,3 +146,21 @@ def test_cancel_and_shutdown():
     t0 = time.perf_counter()
     srv.close()
     assert time.perf_counter() - t0 < 1.0
+
+
+def test_poll_reports_done_and_status():
+    """pc_server_poll's form: (done, status) while a request waits, runs,
+    finishes or is cancelled; pc_server_query keeps the full record."""
+    with pc.Server(slots=1, hbm_budget_bytes=1 << 40, fake_us_per_kpoint=US_PER_KPT) as srv:
+        a = srv.submit(pts(3000), "ward")  # 60 ms
+        b = srv.submit(pts(100, 1), "ward")
+        time.sleep(0.005)
+        assert srv.done(a) == (False, -6)
+        assert srv.done(b) == (False, -6)
+        srv.cancel(b)
+        assert srv.done(b) == (True, -7)
+        srv.wait(a)
+        assert srv.done(a) == (True, 0)
+        assert srv.poll(a)["state"] == "done"
+        with pytest.raises(PCError):
+            srv.done(12345)
