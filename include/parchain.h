@@ -35,7 +35,7 @@ typedef enum {
     PC_ERR_NONFINITE_INPUT = -2, /* a coordinate is NaN or +-Inf */
     PC_ERR_OUT_OF_MEMORY = -3,   /* device workspace does not fit */
     PC_ERR_DEVICE = -4,          /* a HIP runtime call failed */
-    PC_ERR_UNSUPPORTED = -5,     /* valid request this build does not serve */
+    PC_ERR_UNSUPPORTED = -5,     /* a valid request the library does not serve */
     PC_ERR_BUSY = -6,            /* context in use by another thread */
     PC_ERR_CANCELLED = -7
 } pc_status;
