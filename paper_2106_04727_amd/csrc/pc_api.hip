@@ -366,12 +366,16 @@ constexpr long long kMaxRecord = 1LL << 30;
 // the call (two arrays taken in turn), plus the tickets.
 static pc_status grow_part(pc_context *ctx, State &S, long long longest_scan) {
   const long long need = 2 * (longest_scan / 1024 + 1024) + 1;
-  void *old = ctx->cur->part.p;
+  const void *old = ctx->cur->part.p;
+  const size_t old_bytes = ctx->cur->part.bytes;
   HIPCHK(grow(ctx, ctx->cur->part, (size_t)need * sizeof(long long)));
   S.part = (long long *)ctx->cur->part.p;
   S.part_cap = (long long)(ctx->cur->part.bytes / sizeof(long long));
-  // new memory (or a first use in this call) holds stale status words
-  if (ctx->cur->part.p != old || S.sws.st[0] != (unsigned long long *)S.part)
+  // new memory (a reallocation can return the same address, so its size is
+  // compared too) or a first use in this call: stale status words, and the
+  // capacity to take from the new size
+  if (ctx->cur->part.p != old || ctx->cur->part.bytes != old_bytes ||
+      S.sws.st[0] != (unsigned long long *)S.part || S.sws.cap != (int)std::min<long long>((S.part_cap - 1) / 2, 0x7fffffffLL))
     scan_ws_carve(S.sws, S.part, S.part_cap, &S.cnt->scan_err);
   return PC_OK;
 }

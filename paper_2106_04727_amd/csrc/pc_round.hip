@@ -3160,12 +3160,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
     bb = __builtin_amdgcn_readfirstlane(ds.z + c0);
   };
   // consecutive tiles of a candidate share their rows (tiles run row by
-  // row): those are kept in LDS and only the columns are loaded again
+  // row): above K = 32 those are kept in LDS and only the columns are loaded
+  // again (at small K the operands are cheap and the test costs more)
+  constexpr bool kKeepRows = KP > 32;
   int last_ba = -1, last_nr = -1;
   bool cur_reuse = false;
   auto fetch = [&](long long tile) {
     locate(tile);
-    const bool reuse = ba == last_ba && nr == last_nr;
+    const bool reuse = kKeepRows && ba == last_ba && nr == last_nr;
     last_ba = ba;
     last_nr = nr;
 #pragma unroll
@@ -3281,9 +3283,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_cand_tiles(State S, int ncand) {
     }
     __syncthreads();
     const long long nxt = next_tile(tile + 1);  // its points in flight during the tile's arithmetic
-    // a wavefront whose 32 x 32 quarter holds no point pair (small clusters)
-    // skips its matrix and epilogue work; it still meets every barrier
-    const bool wlive = wr < nr && wc < ncl;
+    // above K = 32, a wavefront whose 32 x 32 quarter holds no point pair
+    // (small clusters) skips its matrix and epilogue work; it still meets
+    // every barrier
+    const bool wlive = !kKeepRows || (wr < nr && wc < ncl);
     float16v acc = {};
     if (wlive) {
 #pragma unroll
