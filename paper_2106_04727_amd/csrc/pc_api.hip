@@ -683,6 +683,10 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
   // hands the terminal to the block search
   S.cell_budget = centroid_link(linkage) ? 24 : 160;  // measured on the 1M 2-D workload
   if (const char *e = getenv("PC_CELL_BUDGET")) S.cell_budget = std::max(1, atoi(e));
+  // tuning knob: active clusters at or below which the ring search's first
+  // pass runs a wavefront per terminal (0: never)
+  S.wave_terms = centroid_link(linkage) ? 0 : 60000;  // swept on the 1M 2-D workload
+  if (const char *e = getenv("PC_WAVE_TERMS")) S.wave_terms = std::max(0, atoi(e));
   // tuning knob: active clusters at or below which a grid-path round scans
   // them all instead of walking rings (0: never)
   S.full_scan_max = centroid_link(linkage) ? 2048 : 4096;  // swept on the 1M 2-D workload

@@ -1080,6 +1080,237 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid(State S, int *t_ovf) {
   count_add(&S.cnt->cache_hits, hits);
 }
 
+// ------------------------------------------ ring search, wave per terminal --
+// Rounds with few terminals leave most of the chip idle under one thread per
+// terminal, and each thread's walk is a long chain of dependent loads. Here
+// the 64 lanes of a wavefront share one terminal: a ring is cut into its row
+// and column segments (contiguous item ranges), the items of all segments are
+// dealt out to the lanes, and the lanes' bounds and best candidates are
+// combined at the end of every ring, where the stop rule is applied. Inside a
+// ring a lane prunes with its own bound, never below the combined one, so it
+// keeps every item the thread search would keep; the exact best candidate,
+// hence the row, is the same. Pass 0 only, no pair cache: it writes what
+// pass 1 and the candidate emission read (best candidate, final bound,
+// hand-off flag, recorded large candidates).
+template <int LINK, int MAXD>
+__device__ __forceinline__ void grid_item_p0(const State &S, int it, int t, int cid_t, int n_t, int beg_t,
+                                             const double *ct, const float *lt, const float *ht, double nt,
+                                             double vt, double sp_t, int ti, double &bound, double &bestv,
+                                             unsigned long long &bestk, long long &evals, long long &ppairs) {
+  const int d = S.d;
+  const int4 mt = S.item_meta[it];
+  const int s = mt.x;
+  if (s == t) return;
+  const double *cc = S.item_cen + (size_t)it * d;
+  const unsigned long long key = make_key(mt.z, s);
+  double cv[MAXD];
+  if (centroid_link(LINK)) {
+#pragma unroll
+    for (int q = 0; q < MAXD; ++q) cv[q] = q < d ? cc[q] : 0.0;
+    const double v = cen_key<LINK, MAXD>(ct, nt, vt, cv, (double)mt.y, LINK == kAvgSq ? S.item_v[it] : 0.0, d);
+    ++evals;
+    if (v <= bound && better(v, key, bestv, bestk)) {
+      bestv = v;
+      bestk = key;
+    }
+    return;
+  }
+  float lc[MAXD], hc[MAXD];
+#pragma unroll
+  for (int q = 0; q < MAXD; ++q) {
+    cv[q] = q < d ? cc[q] : 0.0;
+    lc[q] = q < d ? S.item_lo[(size_t)it * d + q] : 0.f;
+    hc[q] = q < d ? S.item_hi[(size_t)it * d + q] : 0.f;
+  }
+  double lb, ub;
+  pair_bounds<LINK, MAXD>(ct, lt, ht, cv, lc, hc, d, lb, ub, sp_t + (double)__int_as_float(mt.w));
+  if (lb > fmin(bound, bestv) * kSlack) return;
+  const long long cost = (long long)n_t * (long long)mt.y;
+  if (cost > kInlinePairs) {
+    // remember it: the final bound decides later whether it is evaluated
+    const long long ci = append_slot(&S.cnt->n_cand);
+    if (ci < S.cand_cap) {
+      S.cd_t[ci] = ti;
+      S.cd_c[ci] = s;
+      S.cd_lb[ci] = lb;
+    } else {
+      S.cnt->cand_overflow = 1;
+    }
+    if (LINK == kComplete) comp_ub_refine(S, t, s, ct, cv, d, ub);
+    if (ub < bound) bound = ub;
+    return;
+  }
+  double v;
+  if (cost == 1) {
+    double q = 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k)
+      if (k < d) {
+        const double u = ct[k] - cv[k];
+        q += u * u;
+      }
+    v = LINK == kComplete ? q : sqrt(q);
+  } else {
+    const int beg_c = S.cbeg[s];
+    v = (mt.z < cid_t) ? pair_exact_inline<LINK>(S.px, d, beg_c, mt.y, beg_t, n_t)
+                       : pair_exact_inline<LINK>(S.px, d, beg_t, n_t, beg_c, mt.y);
+  }
+  ++evals;
+  ppairs += cost;
+  if (better(v, key, bestv, bestk)) {
+    bestv = v;
+    bestk = key;
+  }
+}
+
+template <int LINK, int MAXD>
+__global__ __launch_bounds__(kBlock) void k_nn_grid_wave(State S, int *t_ovf) {
+  constexpr int kW = kBlock / kWave;
+  const int nterm = S.cnt->n_term;
+  const int lane = threadIdx.x & (kWave - 1);
+  long long evals = 0, ppairs = 0, visits = 0;
+  const GridParams g = *S.grid;
+  const int d = S.d;
+  const double nmin = (double)S.cnt->n_min;
+  // the loop bound depends on the wavefront only: every lane of a wave runs
+  // the same terminals, so the shuffles below see all 64 lanes
+  for (int ti = blockIdx.x * kW + (int)(threadIdx.x / kWave); ti < nterm; ti += gridDim.x * kW) {
+    const int t = S.term[ti];
+    const int cid_t = S.cid[t];
+    const int n_t = S.csize[t];
+    const double nt = (double)n_t;
+    double ct[MAXD];
+    float lt[MAXD], ht[MAXD];
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k) {
+      ct[k] = k < d ? S.wcen[(size_t)t * d + k] : 0.0;
+      lt[k] = (!centroid_link(LINK) && k < d) ? S.lo[(size_t)t * d + k] : 0.f;
+      ht[k] = (!centroid_link(LINK) && k < d) ? S.hi[(size_t)t * d + k] : 0.f;
+    }
+    const int beg_t = !centroid_link(LINK) ? S.cbeg[t] : 0;
+    const double vt = LINK == kAvgSq ? S.cmv[t] : 0.0;
+    const double sp_t = LINK == kComplete ? spread_lo(S, t) : vt;
+    double bound = beta_key<LINK>(S.predd[t]);
+    double bestv = INFINITY;
+    unsigned long long bestk = kNoKey;
+    const int cx = cell_coord(ct[0], g.org[0], g.inv_h, g.G[0]);
+    const int cy = g.axes == 2 ? cell_coord(ct[1], g.org[1], g.inv_h, g.G[1]) : 0;
+    double m = 0.5;
+    {
+      double f = (ct[0] - g.org[0]) * g.inv_h - (double)cx;
+      f = f < 0 ? 0 : (f > 1 ? 1 : f);
+      m = fmin(m, fmin(f, 1.0 - f));
+      if (g.axes == 2) {
+        double f1 = (ct[1] - g.org[1]) * g.inv_h - (double)cy;
+        f1 = f1 < 0 ? 0 : (f1 > 1 ? 1 : f1);
+        m = fmin(m, fmin(f1, 1.0 - f1));
+      }
+    }
+    const int kmax = max(max(cx, g.G[0] - 1 - cx), max(cy, g.G[1] - 1 - cy));
+    int visited = 0;
+    bool overflow = false;
+    for (int k = 0; k <= kmax; ++k) {
+      if (k >= 1) {
+        const double D = fmax(0.0, ((double)(k - 1) + m) * g.h * (1.0 - 1e-9) - g.eps);
+        const double lbk = ring_key_lb<LINK>(D, nt, nmin) + sp_t;
+        if (lbk > fmin(bound, bestv)) break;
+      }
+      visited += k == 0 ? 1 : 8 * k;
+      if (visited > S.cell_budget) {
+        overflow = true;
+        break;
+      }
+      // segments of ring k: 0 and 1 the rows above and below (full width),
+      // then the left and right column cells between them
+      const int ylo = k == 0 ? 0 : max(cy - k + 1, 0), yhi = k == 0 ? -1 : min(cy + k - 1, g.G[1] - 1);
+      const int ncol = max(0, yhi - ylo + 1);
+      const int nseg = k == 0 ? 1 : 2 + 2 * ncol;
+      for (int s0 = 0; s0 < nseg; s0 += kWave) {
+        const int j = s0 + lane;
+        int a = 0, b = 0;
+        if (j < nseg) {
+          int y, x0, x1;
+          if (k == 0) {
+            y = cy;
+            x0 = x1 = cx;
+          } else if (j < 2) {
+            y = j == 0 ? cy - k : cy + k;
+            x0 = max(cx - k, 0);
+            x1 = min(cx + k, g.G[0] - 1);
+          } else {
+            const int jj = j - 2;
+            y = ylo + (jj < ncol ? jj : jj - ncol);
+            x0 = x1 = jj < ncol ? cx - k : cx + k;
+          }
+          if (y >= 0 && y < g.G[1] && x0 >= 0 && x1 < g.G[0] && x0 <= x1) {
+            a = S.cell_start[y * g.G[0] + x0];
+            b = S.cell_start[y * g.G[0] + x1 + 1];
+          }
+        }
+        // exclusive prefix of the segment lengths over the lanes
+        int incl = b - a;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const int u = __shfl_up(incl, o, kWave);
+          if (lane >= o) incl += u;
+        }
+        const int excl = incl - (b - a);
+        const int total = __shfl(incl, kWave - 1, kWave);
+        const int nsc = min(nseg - s0, kWave);
+        if (lane == 0) visits += total;
+        for (int base = 0; base < total; base += kWave) {
+          const int i = base + lane;
+          // the last segment whose start is at or before i (empty segments
+          // share their start with the next one, so the last is non-empty)
+          int sg = 0;
+#pragma unroll
+          for (int step = kWave / 2; step > 0; step >>= 1) {
+            const int c = sg + step;
+            const int pc = __shfl(excl, c < nsc ? c : 0, kWave);
+            if (c < nsc && pc <= i) sg = c;
+          }
+          const int sa = __shfl(a, sg, kWave), sp = __shfl(excl, sg, kWave);
+          if (i < total)
+            grid_item_p0<LINK, MAXD>(S, sa + (i - sp), t, cid_t, n_t, beg_t, ct, lt, ht, nt, vt, sp_t, ti, bound,
+                                     bestv, bestk, evals, ppairs);
+        }
+      }
+      // combine the lanes: smallest bound, best (value, key)
+      bound = wave_min(bound);
+#pragma unroll
+      for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bestv, o, kWave);
+        const unsigned long long ok = __shfl_xor(bestk, o, kWave);
+        if (better(ov, ok, bestv, bestk)) {
+          bestv = ov;
+          bestk = ok;
+        }
+      }
+    }
+    if (lane == 0) {
+      bool hand_off = overflow;
+      // the predecessor bound was not met (cannot happen for an exact
+      // bound): the full scan takes the terminal without a bound
+      if (!overflow && centroid_link(LINK) && bestk == kNoKey) hand_off = true;
+      t_ovf[ti] = hand_off ? 1 : 0;
+      if (hand_off) {
+        const int o = atomicAdd(&S.cnt->n_ovf, 1);
+        S.ovf[o] = ti;
+      } else {
+        S.t_best[ti] = bestv;
+        S.t_key[ti] = bestk;
+        if (!centroid_link(LINK)) {
+          S.t_beta[ti] = fmin(bound, bestv);
+          S.t_min[ti] = pos_bits(bestv);
+        }
+      }
+    }
+  }
+  count_add(&S.cnt->cluster_evals, evals);
+  count_add(&S.cnt->point_pairs, ppairs);
+  count_add(&S.cnt->visits[0], visits);
+}
+
 // Recorded large candidates: keep those whose lower bound does not exceed
 // their terminal's final bound (refined bounds for complete), emit them as
 // pairs. Does nothing if the record overflowed (the host then re-walks the
@@ -3870,16 +4101,25 @@ void launch_ringblk(State &S, int ob, hipStream_t s) {
   k_nn_ringblk<LINK, MAXD, false><<<ob, kBlock, 0, s>>>(S);
 }
 
+// pass 0 of the ring search: a wavefront per terminal in rounds with few
+// active clusters (no pair cache), else a thread per terminal
+template <int LINK, int MAXD>
+void launch_grid_p0(State &S, int nact, hipStream_t s, int *t_ovf) {
+  if ((centroid_link(LINK) || !S.cache_mask) && nact <= S.wave_terms)
+    k_nn_grid_wave<LINK, MAXD><<<nblk((long long)nact * kWave, 1 << 16), kBlock, 0, s>>>(S, t_ovf);
+  else
+    launch_grid<LINK, MAXD, 0>(S, nblk(nact, 1 << 20), s, t_ovf);
+}
+
 template <int LINK>
 void launch_search(State &S, int nact, hipStream_t s, int *t_ovf) {
-  const int tb = nblk(nact, 1 << 20);
   const size_t sm = (size_t)S.d * (sizeof(double) + 2 * sizeof(float));
   if (S.d <= kGridMaxDim && S.prune) {
     tmark(S, 0, false, s);
-    if (S.d <= 2) launch_grid<LINK, 2, 0>(S, tb, s, t_ovf);
-    else if (S.d <= 4) launch_grid<LINK, 4, 0>(S, tb, s, t_ovf);
-    else if (S.d <= 8) launch_grid<LINK, 8, 0>(S, tb, s, t_ovf);
-    else launch_grid<LINK, 16, 0>(S, tb, s, t_ovf);
+    if (S.d <= 2) launch_grid_p0<LINK, 2>(S, nact, s, t_ovf);
+    else if (S.d <= 4) launch_grid_p0<LINK, 4>(S, nact, s, t_ovf);
+    else if (S.d <= 8) launch_grid_p0<LINK, 8>(S, nact, s, t_ovf);
+    else launch_grid_p0<LINK, 16>(S, nact, s, t_ovf);
     tmark(S, 0, true, s);
     tmark(S, 1, false, s);
     const int ob = nblk((long long)nact * kBlock, 2048);
