@@ -312,6 +312,27 @@ def test_avgsq_hand_computed_instances(pc):
             assert got[key] == pytest.approx(h, rel=1e-15), (inst["name"], A, B)
 
 
+@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("d", [2, 3])
+def test_ring_search_wave_equals_thread(pc, link, d, monkeypatch):
+    """The ring search's first pass takes a thread per terminal or, in rounds
+    with few active clusters, a wavefront per terminal: rows must be the same
+    with the wavefront search never used, used in every grid round, and used
+    with a one-cell budget that hands every terminal on to the block search."""
+    x = synth.blobs(12000, d, 30, 0.02, 80 + d)
+    monkeypatch.setenv("PC_TREE_MAX_DIM", "0")  # the grid also for Ward / avg-2 at d = 3
+    monkeypatch.setenv("PC_WAVE_TERMS", "0")
+    Z0 = pc.hac(x, link, cache_slots=0)
+    monkeypatch.setenv("PC_WAVE_TERMS", "100000000")
+    Z1 = pc.hac(x, link, cache_slots=0)
+    monkeypatch.setenv("PC_CELL_BUDGET", "1")
+    Z2, st = pc.hac(x, link, cache_slots=0, return_stats=True)
+    assert st["overflow_queries"] > 0
+    assert same_rows(Z0, Z1, link) and same_rows(Z0, Z2, link)
+    Zo, _ = oracle.nnchain(x, link, threads=8)
+    assert _trees.same_tree(Z1, Zo, 12000, rtol=RTOL[link])
+
+
 @pytest.mark.parametrize("d", [2, 3, 5])
 def test_avgsq_ring_handoff(pc, d, monkeypatch):
     """avg-2 on the centroid grid (the box tree switched off at d = 3, 5): a
