@@ -685,8 +685,12 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
   if (const char *e = getenv("PC_CELL_BUDGET")) S.cell_budget = std::max(1, atoi(e));
   // tuning knob: active clusters at or below which the ring search's first
   // pass runs a wavefront per terminal (0: never)
-  S.wave_terms = centroid_link(linkage) ? 0 : 60000;  // swept on the 1M 2-D workload
+  // (avg-2: off; its per-item work is too light to pay for combining lanes)
+  S.wave_terms = linkage == kAvgSq ? 0 : (linkage == kWard ? 30000 : 60000);  // swept on the 1M 2-D workload
   if (const char *e = getenv("PC_WAVE_TERMS")) S.wave_terms = std::max(0, atoi(e));
+  // cells a wavefront searches before handing its terminal to the block search
+  S.wave_budget = 640;
+  if (const char *e = getenv("PC_WAVE_BUDGET")) S.wave_budget = std::max(1, atoi(e));
   // tuning knob: active clusters at or below which a grid-path round scans
   // them all instead of walking rings (0: never)
   S.full_scan_max = centroid_link(linkage) ? 2048 : 4096;  // swept on the 1M 2-D workload

@@ -311,6 +311,7 @@ struct State {
   int tb0, tb1;      // terminals [tb0, tb1) of the current Gram batch
   int cell_budget;  // grid cells a thread-per-terminal search visits before handing off
   int wave_terms;   // rounds with at most this many active clusters search a wavefront per terminal
+  int wave_budget;  // grid cells a wavefront-per-terminal search visits before handing off
   int full_scan_max;  // rounds with at most this many active clusters scan them all (grid paths)
   int single;       // this round's clusters are all single points and the search wrote t_best
   double *tile_v;

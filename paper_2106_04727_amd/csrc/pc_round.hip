@@ -1216,7 +1216,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_grid_wave(State S, int *t_ovf) {
         if (lbk > fmin(bound, bestv)) break;
       }
       visited += k == 0 ? 1 : 8 * k;
-      if (visited > S.cell_budget) {
+      if (visited > S.wave_budget) {
         overflow = true;
         break;
       }

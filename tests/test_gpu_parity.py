@@ -325,7 +325,8 @@ def test_ring_search_wave_equals_thread(pc, link, d, monkeypatch):
     Z0 = pc.hac(x, link, cache_slots=0)
     monkeypatch.setenv("PC_WAVE_TERMS", "100000000")
     Z1 = pc.hac(x, link, cache_slots=0)
-    monkeypatch.setenv("PC_CELL_BUDGET", "1")
+    monkeypatch.setenv("PC_CELL_BUDGET", "1")  # thread search
+    monkeypatch.setenv("PC_WAVE_BUDGET", "1")  # wavefront search
     Z2, st = pc.hac(x, link, cache_slots=0, return_stats=True)
     assert st["overflow_queries"] > 0
     assert same_rows(Z0, Z1, link) and same_rows(Z0, Z2, link)
