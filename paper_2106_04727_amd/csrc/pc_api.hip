@@ -693,7 +693,8 @@ static pc_status hac_impl(pc_context *ctx, const float *points, int64_t n, int32
   if (const char *e = getenv("PC_WAVE_BUDGET")) S.wave_budget = std::max(1, atoi(e));
   // tuning knob: active clusters at or below which a grid-path round scans
   // them all instead of walking rings (0: never)
-  S.full_scan_max = centroid_link(linkage) ? 2048 : 4096;  // swept on the 1M 2-D workload
+  // (complete: 1024 since its late rounds search a wavefront per terminal)
+  S.full_scan_max = centroid_link(linkage) ? 2048 : (linkage == kComplete ? 1024 : 4096);  // swept on the 1M 2-D workload
   if (const char *e = getenv("PC_FULL_SCAN_MAX")) S.full_scan_max = std::max(0, atoi(e));
   long long gram_batch = 0;  // terminals per Gram batch (0: all), kept across rounds
   // test hook: small batches exercise the batch loop on small inputs
